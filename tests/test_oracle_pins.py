@@ -1,0 +1,402 @@
+"""Pins for the CPU oracle: each check ties an oracle function to something other
+than itself -- published known-answer vectors, library routines, exact rational
+arithmetic, closed forms, the paper's worked outcomes and bounds.  CPU only."""
+import math
+import os
+from fractions import Fraction
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import scipy.stats as sst
+import torch
+
+from workloads import make_problem
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+U64 = 2.0 ** -53
+
+
+def relerr(x, y):
+    return float(np.linalg.norm(np.asarray(x) - np.asarray(y)) / np.linalg.norm(y))
+
+
+# ---------------------------------------------------------------- generator
+
+def test_philox_known_answers(orc):
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt"))
+            if l.strip() and not l.startswith("#")]
+    assert len(rows) == 3
+    for r in rows:
+        v = [int(t, 16) for t in r]
+        out = orc.philox4x32_10(v[0:4], v[4:6])
+        assert [int(o) for o in out] == v[6:10]
+
+
+def test_omega_is_standard_normal(orc):
+    Om = orc.omega(seed=12345, s=16, m=8192)
+    z = Om.ravel()
+    assert abs(z.mean()) < 4.0 / math.sqrt(z.size)
+    assert abs(z.var() - 1.0) < 0.03
+    assert sst.kstest(z, "norm").pvalue > 1e-3
+    # rows produced by different counter words must be uncorrelated
+    c = np.corrcoef(Om)
+    off = c[~np.eye(c.shape[0], dtype=bool)]
+    assert np.max(np.abs(off)) < 0.06
+
+
+def test_omega_counter_layout(orc):
+    # every entry depends on (seed, pid, i, j); changing any of them changes it
+    base = orc.lib().oracle_omega_entry(7, 0, 5, 11)
+    assert base == orc.lib().oracle_omega_entry(7, 0, 5, 11)
+    for args in [(8, 0, 5, 11), (7, 1, 5, 11), (7, 0, 6, 11), (7, 0, 5, 12), (7 + (1 << 32), 0, 5, 11)]:
+        assert orc.lib().oracle_omega_entry(*args) != base
+
+
+# ---------------------------------------------------------------- rounding
+
+def test_rounding_matches_library_conversions(orc):
+    rng = np.random.default_rng(3)
+    x32 = np.concatenate([rng.standard_normal(4000) * 10.0 ** rng.uniform(-6, 4, 4000),
+                          [0.0, 1.0, -1.0, 2.0 ** -130, 1.0 + 2.0 ** -8, 1.0 + 3 * 2.0 ** -9]]
+                         ).astype(np.float32)
+    xd = x32.astype(np.float64)
+    ref_bf16 = torch.tensor(x32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.round_to(xd, "bf16"), ref_bf16)
+    ref_fp16 = x32.astype(np.float16).astype(np.float64)
+    np.testing.assert_array_equal(orc.round_to(xd, "fp16"), ref_fp16)
+    small = xd[np.abs(xd) <= 448.0]
+    ref_e4m3 = torch.tensor(small.astype(np.float32)).to(torch.float8_e4m3fn).to(torch.float64).numpy()
+    np.testing.assert_array_equal(orc.round_to(small, "fp8"), ref_e4m3)
+    # e4m3 saturates instead of overflowing
+    np.testing.assert_array_equal(orc.round_to(np.array([500.0, -1e6, 470.0]), "fp8"),
+                                  [448.0, -448.0, 448.0])
+    np.testing.assert_array_equal(orc.round_to(np.array([1e10]), "fp16"), [np.inf])
+
+
+# ---------------------------------------------------------------- sketch
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16"])
+def test_sketch_elementwise_precisions(orc, prec):
+    rng = np.random.default_rng(5)
+    m, n, s = 300, 7, 13
+    A = np.asfortranarray(rng.standard_normal((m, n)))
+    Om = orc.omega(seed=99, s=s, m=m)
+    if prec == "fp64":
+        Oq, Aq = Om, A
+    else:
+        tdt = torch.float32 if prec == "fp32" else torch.bfloat16
+        cv = lambda M: torch.tensor(M.astype(np.float32)).to(tdt).to(torch.float64).numpy()
+        Oq, Aq = cv(Om), cv(A)
+    ref = (Oq @ Aq) / math.sqrt(s)
+    got = orc.sketch(A, s, seed=99, prec=prec)
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-13 * float((np.abs(Oq) @ np.abs(Aq)).max()))
+
+
+@pytest.mark.parametrize("prec", ["fp16", "fp8"])
+def test_sketch_block_scaled(orc, prec):
+    rng = np.random.default_rng(6)
+    m, n, s, br = 300, 5, 9, 128     # 300 rows: two full blocks and a ragged one
+    A = rng.standard_normal((m, n)) * np.array([1.0, 1e-6, 1e3, 2.0 ** -20, 7.0])
+    A[130:256, 3] = 0.0               # an all-zero block
+    A = np.asfortranarray(A)
+    Om = orc.omega(seed=4, s=s, m=m)
+    A32 = torch.tensor(A.astype(np.float32))
+    if prec == "fp16":
+        Oq = torch.tensor(Om.astype(np.float32)).to(torch.float16).to(torch.float64)
+    else:
+        Oq = torch.tensor(Om.astype(np.float32)).clamp(-448, 448).to(torch.float8_e4m3fn).to(torch.float64)
+    ref = torch.zeros(s, n, dtype=torch.float64)
+    for k0 in range(0, m, br):
+        blk = A32[k0:k0 + br]
+        amax = blk.abs().max(dim=0).values
+        if prec == "fp16":
+            e = torch.floor(torch.log2(amax.double()))
+            scale = torch.where(amax > 0, 2.0 ** (e - 14), torch.zeros_like(e)).float()
+        else:
+            scale = torch.where(amax > 0, amax / 448.0, torch.zeros_like(amax))
+        safe = torch.where(scale > 0, scale, torch.ones_like(scale))
+        t = blk / safe
+        if prec == "fp16":
+            q = t.to(torch.float16).to(torch.float64)
+        else:
+            q = t.clamp(-448, 448).to(torch.float8_e4m3fn).to(torch.float64)
+        q = torch.where(scale > 0, q, torch.zeros_like(q))
+        ref += (Oq[:, k0:k0 + br] @ q) * scale.double()
+    ref = ref.numpy() / math.sqrt(s)
+    got = orc.sketch(A, s, seed=4, prec=prec, block_rows=br)
+    np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-300)
+
+
+def test_sketch_subspace_embedding(orc):
+    # For orthonormal U the sketch Omega U / sqrt(s) has singular values in
+    # [1 - sqrt(n/s), 1 + sqrt(n/s)] up to fluctuations (Marchenko-Pastur).
+    rng = np.random.default_rng(8)
+    m, n, s = 4000, 40, 120
+    U, _ = np.linalg.qr(rng.standard_normal((m, n)))
+    sv = np.linalg.svd(orc.sketch(np.asfortranarray(U), s, seed=3), compute_uv=False)
+    lo, hi = 1 - math.sqrt(n / s), 1 + math.sqrt(n / s)
+    assert 0.75 * lo < sv.min() and sv.max() < 1.15 * hi
+
+
+# ---------------------------------------------------------------- QR pieces
+
+def test_householder_r_matches_lapack(orc):
+    rng = np.random.default_rng(9)
+    W = rng.standard_normal((60, 25)) @ np.diag(np.logspace(0, -6, 25))
+    R = orc.householder_r(W)
+    Rl = np.linalg.qr(W, mode="r")
+    sg = np.sign(np.diag(Rl)) * np.sign(np.diag(R))
+    np.testing.assert_allclose(R, sg[:, None] * Rl, rtol=0, atol=1e-13)
+    assert np.all(np.tril(R, -1) == 0)
+    # LAPACK sign convention: beta = -sign(alpha) ||x||
+    W2 = np.array([[3.0, 1.0], [4.0, 2.0], [0.0, 5.0]])
+    R2 = orc.householder_r(W2)
+    assert R2[0, 0] == pytest.approx(-5.0)
+
+
+def _exact_ls(A, b):
+    """Least squares by exact rational arithmetic on A^T A x = A^T b."""
+    m, n = len(A), len(A[0])
+    M = [[sum(Fraction(A[k][i]) * A[k][j] for k in range(m)) for j in range(n)]
+         + [sum(Fraction(A[k][i]) * b[k] for k in range(m))] for i in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c] / M[c][c]
+                M[r] = [a - f * bb for a, bb in zip(M[r], M[c])]
+    return [M[i][n] / M[i][i] for i in range(n)]
+
+
+def _tiny_cases():
+    rng = np.random.default_rng(10)
+    out = []
+    while len(out) < 12:
+        m = int(rng.integers(2, 7))
+        n = int(rng.integers(1, min(m, 3) + 1))
+        A = rng.integers(-5, 6, size=(m, n)).astype(float)
+        if np.linalg.matrix_rank(A) < n:
+            continue
+        b = rng.integers(-9, 10, size=m).astype(float)
+        out.append((A, b))
+    return out
+
+
+def test_qr_ls_exact_rational(orc):
+    for A, b in _tiny_cases():
+        xe = np.array([float(v) for v in _exact_ls(A.tolist(), b.tolist())])
+        x = orc.qr_ls(A, b)
+        assert np.allclose(x, xe, rtol=1e-13, atol=1e-13 * np.abs(xe).max())
+
+
+@pytest.mark.parametrize("hpne", [False, True])
+def test_pne_hpne_exact_rational(orc, hpne):
+    # In exact arithmetic PNE and HPNE give the least-squares solution for any
+    # nonsingular R_s; with FP64 throughout they must agree to rounding.
+    for A, b in _tiny_cases():
+        m, n = A.shape
+        xe = np.array([float(v) for v in _exact_ls(A.tolist(), b.tolist())])
+        r = orc.solve(A, b, hpne=hpne, s=max(3 * n, m), seed=2)
+        assert r["info"] == 0
+        assert np.allclose(r["x"], xe, rtol=1e-11, atol=1e-11 * np.abs(xe).max())
+
+
+def test_qr_ls_error_obeys_lemma(orc):
+    # Lemma 1.1: error <= kappa eps (1 + kappa * residual), eps ~ rounding of A
+    for kappa, rho in [(1e2, 1e-2), (1e4, 1e-6), (1e6, 1e-3)]:
+        p = make_problem(800, 40, kappa, rho, seed=11)
+        x = orc.qr_ls(p.numpy_A(), p.numpy_b())
+        err = relerr(x, p.numpy_x_star())
+        bound = kappa * U64 * (1 + kappa * rho)
+        assert err <= 50 * math.sqrt(800 * 40) * bound
+        assert err >= 1e-3 * bound or err < 1e-14
+
+
+def test_qr_ls_matches_lstsq(orc):
+    p = make_problem(2000, 60, 1e5, 1e-5, seed=12)
+    A, b = p.numpy_A(), p.numpy_b()
+    x = orc.qr_ls(A, b)
+    xl = np.linalg.lstsq(A, b, rcond=None)[0]
+    assert relerr(x, xl) < 1e5 * 1e-14
+
+
+# ---------------------------------------------------------------- A_p, Gram, factorizations
+
+def test_precondition_matches_triangular_solve(orc):
+    rng = np.random.default_rng(13)
+    A = np.asfortranarray(rng.standard_normal((200, 30)))
+    R = np.triu(rng.standard_normal((30, 30))) + 5 * np.eye(30)
+    Ap, info = orc.precondition(A, R)
+    assert info == 0
+    ref = sla.solve_triangular(R, A.T, trans="T", lower=False).T  # A R^{-1}
+    np.testing.assert_allclose(Ap, ref, rtol=1e-12, atol=1e-13)
+    R[7, 7] = 0.0
+    assert orc.precondition(A, R)[1] == 1008
+
+
+def test_gram_matches_matmul(orc):
+    rng = np.random.default_rng(14)
+    X, Y = rng.standard_normal((150, 12)), rng.standard_normal((150, 12))
+    b = rng.standard_normal(150)
+    C, c = orc.gram(X, Y, b)
+    np.testing.assert_allclose(C, X.T @ Y, rtol=1e-13, atol=1e-12)
+    np.testing.assert_allclose(c, X.T @ b, rtol=1e-13, atol=1e-12)
+
+
+def test_cholesky_matches_lapack_and_breakdown(orc):
+    rng = np.random.default_rng(15)
+    M = rng.standard_normal((40, 20))
+    C = M.T @ M
+    L, info = orc.cholesky(C)
+    assert info == 0
+    np.testing.assert_allclose(L, np.linalg.cholesky(C), rtol=1e-12, atol=1e-12)
+    D = np.diag([4.0, 1.0, -1.0, 2.0])
+    assert orc.cholesky(D)[1] == 2003
+    y = orc.cholesky_solve(L, np.arange(20.0))
+    np.testing.assert_allclose(y, np.linalg.solve(C, np.arange(20.0)), rtol=1e-10)
+
+
+def test_lu_matches_lapack(orc):
+    rng = np.random.default_rng(16)
+    C = rng.standard_normal((25, 25))
+    LU, piv, info = orc.lu(C)
+    assert info == 0
+    lu_ref, piv_ref = sla.lu_factor(C)
+    np.testing.assert_array_equal(piv, piv_ref)
+    np.testing.assert_allclose(LU, lu_ref, rtol=1e-12, atol=1e-12)
+    c = rng.standard_normal(25)
+    np.testing.assert_allclose(orc.lu_solve(LU, piv, c), np.linalg.solve(C, c), rtol=1e-10)
+    # ties: the first row of largest magnitude is the pivot (LAPACK i?amax)
+    T = np.array([[1.0, 2.0, 0.0], [-1.0, 1.0, 1.0], [1.0, 0.0, 3.0]])
+    _, pt, _ = orc.lu(T)
+    assert pt[0] == 0
+    _, pz, iz = orc.lu(np.array([[0.0, 1.0], [0.0, 2.0]]))
+    assert iz == 3001
+
+
+def test_upper_solve(orc):
+    rng = np.random.default_rng(17)
+    R = np.triu(rng.standard_normal((15, 15))) + 3 * np.eye(15)
+    y = rng.standard_normal(15)
+    x, info = orc.upper_solve(R, y)
+    assert info == 0
+    np.testing.assert_allclose(x, sla.solve_triangular(R, y), rtol=1e-12)
+    R[4, 4] = 0.0
+    x, info = orc.upper_solve(R, y)
+    assert info == 1005 and np.all(np.isnan(x))
+
+
+# ---------------------------------------------------------------- Algorithm 1 end to end
+
+def test_pne_hpne_agree_with_qr_solver(orc):
+    # Section 6.2: in double precision PNE/HPNE are as accurate as the QR
+    # solver once the relative residual exceeds 1e-4 (m = 6000, n = 100,
+    # kappa = 1e4).
+    for rho in [1e-3, 1e-1]:
+        p = make_problem(6000, 100, 1e4, rho, seed=20)
+        A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+        eq = relerr(orc.qr_ls(A, b), xs)
+        for hpne in (False, True):
+            r = orc.solve(A, b, hpne=hpne, s=300, seed=1)
+            assert r["info"] == 0
+            assert relerr(r["x"], xs) <= 3 * eq + 1e-15
+
+
+def test_mixed_fp32_preconditioner_accuracy(orc):
+    # Section 6.3: with a single precision preconditioner at kappa = 1e8 the
+    # error is within about a factor 100 of the QR solver for small residuals
+    # and as accurate for large ones.
+    for rho, factor in [(1e-8, 300.0), (1e-2, 5.0)]:
+        p = make_problem(6000, 100, 1e8, rho, seed=21)
+        A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+        eq = relerr(orc.qr_ls(A, b), xs)
+        for hpne in (False, True):
+            r = orc.solve(A, b, hpne=hpne, s=300, seed=1, sketch_prec="fp32", qr_prec="fp32")
+            assert r["info"] == 0
+            assert relerr(r["x"], xs) <= factor * eq
+
+
+def test_kappa_Ap_closed_form(orc):
+    # Gaussian sketch, s = 3n, exact preconditioner: kappa(A_p) = kappa(Omega U),
+    # asymptotically (1 + sqrt(1/3)) / (1 - sqrt(1/3)) = 3.73.
+    p = make_problem(3000, 60, 1e6, 1e-6, seed=22)
+    A = p.numpy_A()
+    r = orc.solve(A, p.numpy_b(), s=180, seed=5)
+    Ap, info = orc.precondition(A, r["R"])
+    sv = np.linalg.svd(Ap, compute_uv=False)
+    assert 2.0 < sv[0] / sv[-1] < 6.0
+
+
+def test_rscond_lemma_for_fp32_preconditioner(orc):
+    # Lemma 5.1: kappa(A R1^{-1}) <= kappa(A_p) (1 + e k(R_s)) / (1 - e k(R_s))
+    p = make_problem(3000, 60, 1e5, 1e-6, seed=23)
+    A, b = p.numpy_A(), p.numpy_b()
+    R64 = orc.solve(A, b, s=180, seed=5)["R"]
+    R32 = orc.solve(A, b, s=180, seed=5, sketch_prec="fp32", qr_prec="fp32")["R"]
+    kap = lambda M: (lambda sv: sv[0] / sv[-1])(np.linalg.svd(M, compute_uv=False))
+    k_ap = kap(orc.precondition(A, R64)[0])
+    k_a1 = kap(orc.precondition(A, R32)[0])
+    eps = np.linalg.norm(R32 - R64, 2) / np.linalg.norm(R64, 2)
+    ek = eps * kap(R64)
+    assert ek < 1
+    assert k_a1 <= k_ap * (1 + ek) / (1 - ek) * 1.0001
+
+
+def test_refinement_restores_accuracy(orc):
+    p = make_problem(3000, 50, 1e6, 1e-4, seed=24)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    eq = relerr(orc.qr_ls(A, b), xs)
+    r0 = orc.solve(A, b, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=0)
+    r2 = orc.solve(A, b, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
+    assert relerr(r0["x"], xs) > 10 * eq       # the BF16 preconditioner alone is not enough
+    assert relerr(r2["x"], xs) <= 10 * eq      # two FP64 corrections are
+
+
+# ---------------------------------------------------------------- condition estimate
+
+def _golden_selection():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "precision_selection.txt"))
+            if l.strip() and not l.startswith("#")]
+    return [(float(k), int(n), int(c)) for k, n, c in rows]
+
+
+@pytest.mark.parametrize("kappa,n,code", _golden_selection())
+def test_precision_pick_worked_cases(orc, kappa, n, code):
+    p = make_problem(10 * n, n, kappa, 1e-6, seed=30)
+    k0, k0n, ch = orc.cond_est(p.numpy_A())
+    assert ch == code
+
+
+def test_cond_est_is_a_good_lower_estimate(orc):
+    # Hager's estimate never exceeds the 1-norm of the inverse (in exact
+    # arithmetic; the FP32 solves perturb it by about u32 kappa(G), so the
+    # strict check uses kappa(A) <= 3e2) and is within a factor 10 of it.
+    for kappa in [1e1, 1e2, 3e2, 3e3]:
+        p = make_problem(2000, 50, kappa, 1e-6, seed=31)
+        A32 = p.numpy_A().astype(np.float32).astype(np.float64)
+        G = A32.T @ A32
+        exact = 0.5 * math.log10(np.abs(G).sum(0).max() * np.abs(np.linalg.inv(G)).sum(0).max())
+        k0, k0n, ch = orc.cond_est(p.numpy_A())
+        slack = 1e-3 if kappa <= 3e2 else 0.5 * math.log10(1 + 2 ** -23 * kappa ** 2)
+        assert k0 <= exact + slack
+        assert k0 >= exact - 0.5
+        assert k0n == pytest.approx(k0 + 0.5 * math.log10(50), abs=1e-4)
+        # the 2-norm condition number sits below the 1-norm bound with factor n
+        assert math.log10(kappa) <= k0n + 0.05
+
+
+def test_known_kappa_thresholds(orc):
+    A = np.eye(3)
+    assert orc.cond_est(A, known_kappa=1e2)[2] == 3
+    assert orc.cond_est(A, known_kappa=1e4)[2] == 2      # kappa0 = 4 is not < 4
+    assert orc.cond_est(A, known_kappa=1e8)[2] == 2      # kappa0 = 8 is <= 8
+    assert orc.cond_est(A, known_kappa=1.1e8)[2] == 1
+
+
+def test_invalid_arguments(orc):
+    A = np.ones((3, 4))
+    with pytest.raises(ValueError):
+        orc.qr_ls(A, np.ones(3))
+    assert orc.solve(np.eye(4), np.ones(4), s=2)["info"] == -1
