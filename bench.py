@@ -1,0 +1,227 @@
+#!/usr/bin/env python3
+"""Throughput of the randomized PNE least-squares solve on one MI355X.
+
+Workload (single problem): m = 100,000, n = 1,000, kappa(A) = 1e6 (geometric
+singular values), relative residual 1e-4, Gaussian sketch s = 3,000.  One
+step = one complete pne_solve (sketch, sketch QR, A R_s^{-1}, Gram, Cholesky,
+triangular solves, FP64 refinement) on inputs already resident in HBM.
+
+The headline is the mixed-precision path (BF16 sketch with FP32
+accumulation, FP32 QR, one FP64 refinement step); the all-FP64 path and the
+FP32 preconditioner are timed beside it on the same input, with their
+errors against the known solution.  Prints one JSON line.
+
+  python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+M, N, KAPPA, RHO, S = 100_000, 1000, 1e6, 1e-4, 3000
+WORKLOAD = "ls_100000x1000_k1e6_rho1e-4_s3000"
+METRIC = "LS solves/sec + MFMA roofline %, mixed vs FP64 PNE/HPNE at equal rel. error"
+PEAK_FP64 = 78.6e12      # dense FP64 MFMA, FLOP/s
+PEAK_BF16 = 2.5e15       # dense BF16 MFMA, FLOP/s
+PEAK_HBM = 8.0e12        # B/s
+U64 = 2.0 ** -53
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--quick", action="store_true", help="mixed path only (profiling runs)")
+    return ap.parse_args()
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2603_16644_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def time_solver(pne, prob, opts, steps, warmup, hpne=False, profile=False):
+    import torch
+    fn = pne.hpne_solve if hpne else pne.pne_solve
+    x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    L = pne.lib()
+    for _ in range(warmup):
+        fn(prob.A, prob.b, x=x, opts=opts)
+    torch.cuda.synchronize()
+    phases = []
+    if profile:
+        L.pne_profile_enable(1)
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            _, info, _ = fn(prob.A, prob.b, x=x, opts=opts)
+            if profile:
+                ms = (ctypes.c_double * 16)()
+                cnt = L.pne_profile_read(ms, 16)
+                phases.append({L.pne_profile_phase_name(i).decode(): ms[i] for i in range(cnt)})
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        if profile:
+            L.pne_profile_enable(0)
+    assert int(info.item()) == 0, f"solver info {int(info.item())}"
+    xs = prob.x_star
+    err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+    return (t1 - t0) / steps, err, phases
+
+
+def mean_phases(phases):
+    keys = phases[0].keys()
+    out = {}
+    for k in keys:
+        v = [p[k] for p in phases if p[k] >= 0]
+        if v:
+            out[k] = sum(v) / len(v)
+    return out
+
+
+def roofline(ph):
+    """Dominant single-kernel phase against its MFMA peak (algorithmic flops)."""
+    cands = {
+        # C = A_p^T A_p (lower triangle incl. diagonal) and c = A_p^T b
+        "gram_gemm": (M * N * (N + 1) + 2 * M * N, PEAK_FP64, "gemm_cm_kernel<double,double,double,128,true>"),
+        # A_s = Omega A, BF16 operands
+        "sketch_gemm": (2 * S * M * N, PEAK_BF16, "gemm_lp_kernel<bf16,false>"),
+    }
+    best = max(cands, key=lambda k: ph.get(k, 0.0))
+    flops, peak, kname = cands[best]
+    t = ph[best] * 1e-3
+    achieved = flops / t
+    traffic = None
+    tf = os.path.join(ROOT, "profiles", "traffic.json")
+    if os.path.exists(tf):
+        try:
+            rec = json.load(open(tf)).get(best)
+            if rec and rec.get("source_hash") == source_hash("gemm.hip", "sketch.hip"):
+                traffic = rec["bytes_per_launch"]
+        except (ValueError, OSError):
+            traffic = None
+    return {"kernel": kname, "phase": best, "bound": "mfma", "achieved": achieved / 1e12,
+            "peak": peak / 1e12, "unit": "TFLOP/s", "frac": achieved / peak, "traffic": traffic,
+            "ms_per_launch": ph[best], "algorithmic_flops": flops}
+
+
+def cpu_baseline(prob, ms_rows=2000):
+    """Oracle (plain single-threaded C, FP64 with BF16 operand emulation) timed
+    per step on the first `ms_rows` rows of the same A; the row-proportional
+    steps are scaled by M / ms_rows, the rest (QR, Cholesky, solves) taken as
+    measured."""
+    import numpy as np
+
+    import oracle
+    A = prob.numpy_A()[:ms_rows]
+    A = np.asfortranarray(A)
+    b = prob.numpy_b()[:ms_rows]
+    oracle.lib()
+    t = {}
+    t0 = time.perf_counter()
+    As = oracle.sketch(A, S, seed=2, prec="bf16")
+    t["sketch"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    R = oracle.householder_r(As.astype(np.float32).astype(np.float64))
+    t["qr"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    Ap, _ = oracle.precondition(A, R)
+    t["trsm"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    C, c = oracle.gram(Ap, Ap, b)
+    t["gram"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    L, info = oracle.cholesky(C)
+    y = oracle.cholesky_solve(L, c)
+    x, _ = oracle.upper_solve(R, y)
+    t["factor_solve"] = time.perf_counter() - t0
+    scale = M / ms_rows
+    # the refinement's two matrix-vector passes (4mn flops) are below 0.1% of
+    # the sketch and are not timed
+    per_solve = scale * (t["sketch"] + t["trsm"] + t["gram"]) + t["qr"] + 2 * t["factor_solve"]
+    sample_s = sum(t.values())
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": (f"oracle steps on the first {ms_rows} of {M} rows (n={N}, s={S}, BF16 operand "
+                       f"emulation, single thread, {sample_s:.1f} s of CPU work); row-proportional steps "
+                       f"(sketch, A R^-1, Gram) scaled by {scale:.0f}x, QR/Cholesky/"
+                       f"solves as measured"),
+            "phase_seconds": {k: round(v, 3) for k, v in t.items()}}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2603_16644_amd as pne
+    from workloads import make_problem
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    print(f"[bench] generating m={M} n={N} kappa={KAPPA:g} rho={RHO:g}", file=sys.stderr, flush=True)
+    prob = make_problem(M, N, KAPPA, RHO, seed=1002, device="cuda")
+    torch.cuda.synchronize()
+    bound = KAPPA * U64 * (1 + KAPPA * RHO)
+
+    mixed = pne.make_opts(s=S, seed=2, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    print("[bench] timing mixed PNE", file=sys.stderr, flush=True)
+    t_mix, e_mix, ph = time_solver(pne, prob, mixed, args.steps, args.warmup, profile=True)
+    phases = mean_phases(ph)
+    out_extra = {}
+    if not args.quick:
+        fp64 = pne.make_opts(s=S, seed=2, sketch_prec="fp64", qr_prec="fp64", refine_steps=0)
+        fp32 = pne.make_opts(s=S, seed=2, sketch_prec="fp32", qr_prec="fp32", refine_steps=0)
+        print("[bench] timing FP64 PNE", file=sys.stderr, flush=True)
+        t64, e64, ph64 = time_solver(pne, prob, fp64, args.steps, args.warmup, profile=True)
+        print("[bench] timing FP32-preconditioner PNE", file=sys.stderr, flush=True)
+        t32, e32, _ = time_solver(pne, prob, fp32, args.steps, args.warmup)
+        print("[bench] timing mixed HPNE", file=sys.stderr, flush=True)
+        th, eh, _ = time_solver(pne, prob, mixed, args.steps, args.warmup, hpne=True)
+        out_extra = {
+            "fp64_pne": {"solves_per_s": 1.0 / t64, "ms": t64 * 1e3, "rel_err": e64,
+                         "phases_ms": {k: round(v, 4) for k, v in mean_phases(ph64).items()}},
+            "fp32_precond_pne": {"solves_per_s": 1.0 / t32, "ms": t32 * 1e3, "rel_err": e32},
+            "mixed_hpne": {"solves_per_s": 1.0 / th, "ms": th * 1e3, "rel_err": eh},
+            "speedup_vs_fp64": t64 / t_mix,
+            "equal_error": bool(e_mix <= 10 * max(e64, bound * 1e-3) and e_mix <= 10 * bound),
+        }
+    line = {
+        "metric": METRIC, "value": 1.0 / t_mix, "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": t_mix * 1e3, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32+f64", "data": "synthetic",
+        "config": {"workload": WORKLOAD, "m": M, "n": N, "kappa": KAPPA, "rho": RHO, "s": S,
+                   "solver": "pne", "sketch_prec": "bf16", "qr_prec": "fp32", "refine_steps": 1,
+                   "parallelism": "single"},
+        "rel_err": e_mix, "lemma_bound": bound,
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "roofline": roofline(phases),
+    }
+    line.update(out_extra)
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle sample", file=sys.stderr, flush=True)
+        line["cpu_baseline"] = cpu_baseline(prob)
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,187 @@
+/*
+ * pne.h -- C ABI of the MI355X (gfx950) library for tall least-squares
+ * problems  min_x ||A x - b||_2,  A m x n with rank n, m >> n,  solved by the
+ * randomized preconditioned normal equations of Garrison & Ipsen,
+ * "Perturbation Analysis for Preconditioned Normal Equations in Mixed
+ * Precision" (arXiv 2603.16644):
+ *
+ *   PNE  (Section 1, eq. e_pne):  A_p^T A_p y = A_p^T b,  R_s x = y
+ *   HPNE (Section 1, eq. e_hpne): A_p^T A x = A_p^T b
+ *   with A_p = A R_s^{-1} and R_s the triangular factor of a sketch
+ *   Omega A (Algorithm 1; Section 5.2), computed in a lower precision.
+ *
+ * Common conventions for every entry point.
+ *   - All matrices are column-major with a leading dimension (LAPACK); A has
+ *     lda >= m.  All array arguments named d* are device pointers on the
+ *     current HIP device, owned by the caller; the library never frees or
+ *     keeps them.  A and b are read only; outputs are overwritten.
+ *   - The library allocates no device memory during a call.  Scratch space
+ *     comes from the caller as dwork/work_bytes (device memory, any
+ *     contents, 256-byte aligned); query its size with the *_workspace_size
+ *     function of the entry point.  Workspace contents are undefined after a
+ *     call.  Two calls that share a workspace must be ordered on one stream.
+ *   - All device work is enqueued on `stream` and is asynchronous, except
+ *     where stated (AUTO precision reads the condition estimate back to pick
+ *     kernels, which synchronises the stream once).
+ *   - Argument errors (n < 1, m < n, s < n, lda < m, null pointers, workspace
+ *     too small, unsupported option) are detected on the host before any
+ *     device work and returned as a negative pne_status; nothing is enqueued.
+ *   - Numerical failures are reported asynchronously in the device word
+ *     *dinfo (LAPACK style): 0 success; 1000+k: R_s(k,k) == 0; 2000+k:
+ *     Cholesky of the PNE matrix broke down at column k; 3000+k: zero pivot
+ *     in the LU of the HPNE matrix at column k (k 1-based).  On failure x is
+ *     filled with NaN; no silent fallback to another precision is taken.
+ *   - Same inputs and options give bitwise identical results (every
+ *     reduction has a fixed order; no floating-point atomics).
+ */
+#ifndef PNE_H
+#define PNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ihipStream_t* pne_stream_t; /* a hipStream_t; NULL = default stream */
+
+typedef enum {
+    PNE_OK = 0,
+    PNE_EINVAL = -1,     /* invalid argument                          */
+    PNE_ENOMEM = -2,     /* host allocation failed                    */
+    PNE_EHIP = -3,       /* a HIP runtime call failed                 */
+    PNE_EWORKSPACE = -4, /* work_bytes smaller than the queried size  */
+    PNE_ENOTSUP = -5     /* option combination not supported          */
+} pne_status;
+
+/* Arithmetic of the preconditioner (Algorithm 1, "precision u_p"). */
+typedef enum {
+    PNE_PREC_AUTO = 0,     /* pick by the FP32 condition estimate (Section 5.1)  */
+    PNE_PREC_FP64 = 1,
+    PNE_PREC_FP32 = 2,
+    PNE_PREC_FP16 = 3,     /* FP16 operands, per-block power-of-two scales of A   */
+    PNE_PREC_BF16 = 4,
+    PNE_PREC_FP8E4M3 = 5   /* OCP e4m3 operands, per-block FP32 scales of A       */
+} pne_prec;
+
+typedef struct {
+    int64_t s;              /* sketch rows; 0 selects 3n (Section 5.2 uses d = 3n)       */
+    uint64_t seed;          /* key of the counter-based Gaussian sketch                  */
+    uint32_t problem_id;    /* third counter word of the sketch (batch member index)     */
+    int32_t sketch_prec;    /* pne_prec of the sketch Omega A                            */
+    int32_t qr_prec;        /* pne_prec of the QR of the sketch (FP8 not allowed)        */
+    double known_kappa;     /* > 0: skip the estimate, pick from log10(known_kappa)      */
+    int32_t refine_steps;   /* FP64 residual corrections after the solve (default 1)     */
+    int32_t block_rows;     /* rows per scale block for FP16/FP8 sketches (128; mult. of 64) */
+} pne_opts;
+
+typedef struct {
+    int32_t sketch_prec_used; /* precision actually used (AUTO resolved)  */
+    int32_t qr_prec_used;
+    float kappa0;             /* (1/2) log10(||G||_1 est ||G^-1||_1), G = fl32(A^T A); NaN if not estimated */
+    int32_t refine_steps_run;
+} pne_info;
+
+/* Fills *opts with the defaults: s = 0 (3n), seed = 0, problem_id = 0,
+ * sketch_prec = qr_prec = AUTO, known_kappa = 0, refine_steps = 1,
+ * block_rows = 128. */
+void pne_default_opts(pne_opts* opts);
+
+/* Bytes of workspace pne_solve (hpne = 0) or hpne_solve (hpne = 1) needs for
+ * an m x n problem with these options.  Returns 0 on invalid arguments. */
+size_t pne_workspace_size(int64_t m, int64_t n, const pne_opts* opts, int hpne);
+
+/* pne_solve: Algorithm 1 with the PNE (Section 1, eq. e_pne; Section 3).
+ *   1. [AUTO] condition estimate and precision pick (see cond_est);
+ *   2. A_s = Omega A, Omega s x m with N(0, 1/s) entries generated on the fly
+ *      from (seed, problem_id, row, column) (Algorithm 1 "Sketch");
+ *   3. Householder QR of A_s in qr_prec, R_s promoted to FP64;
+ *   4. A_p = A R_s^{-1} (FP64, blocked substitution);
+ *   5. C = A_p^T A_p, c = A_p^T b (FP64);
+ *   6. Cholesky C = L L^T, L L^T y = c, R_s x = y (FP64);
+ *   7. refine_steps corrections: r = b - A x, solve the same system with
+ *      right-hand side A_p^T r, x += correction (FP64).
+ * dA: m x n (lda); db: m; dx: n (output).  dinfo: one device int32.
+ * hinfo (host, may be NULL) receives the precisions used; with AUTO the
+ * call synchronises the stream once and fills kappa0.  */
+pne_status pne_solve(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
+                     double* dx, const pne_opts* opts, void* dwork, size_t work_bytes,
+                     int32_t* dinfo, pne_info* hinfo, pne_stream_t stream);
+
+/* hpne_solve: Algorithm 1 with the HPNE (Section 1, eq. e_hpne; Section 4):
+ * steps 1-4 as pne_solve, then C = A_p^T A, c = A_p^T b, LU with partial
+ * pivoting (first index of largest magnitude on ties) P C = L U, and
+ * L U x = P c; refinement as in pne_solve with the LU factors.
+ * Same arguments as pne_solve. */
+pne_status hpne_solve(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
+                      double* dx, const pne_opts* opts, void* dwork, size_t work_bytes,
+                      int32_t* dinfo, pne_info* hinfo, pne_stream_t stream);
+
+/* sketch_precond: the preconditioner alone (Algorithm 1 steps "Sketch",
+ * "Thin QR", "Promote R_s"; Section 5.2).  Writes the upper triangle of the
+ * n x n FP64 matrix R_s into dR (ldr >= n); the strict lower triangle is set
+ * to zero.  Workspace: sketch_precond_workspace_size. */
+size_t sketch_precond_workspace_size(int64_t m, int64_t n, const pne_opts* opts);
+pne_status sketch_precond(int64_t m, int64_t n, const double* dA, int64_t lda, const pne_opts* opts,
+                          double* dR, int64_t ldr, void* dwork, size_t work_bytes, int32_t* dinfo,
+                          pne_info* hinfo, pne_stream_t stream);
+
+/* cond_est: the single-precision condition estimate of Section 5.1 and the
+ * precision pick of Algorithm 1.  G = fl32(A)^T fl32(A) (FP32), FP32
+ * Cholesky, Hager's 1-norm estimate of ||G^{-1}||_1 (at most five
+ * iterations), kappa0 = (1/2) log10(||G||_1 est) written to *dkappa0 (device
+ * float; +inf when the Cholesky breaks down, i.e. the estimate overflows);
+ * *dchoice (device int32) = PNE_PREC_FP16 if kappa0 < 4, PNE_PREC_FP32 if
+ * kappa0 <= 8, else PNE_PREC_FP64.  Workspace: cond_est_workspace_size. */
+size_t cond_est_workspace_size(int64_t m, int64_t n);
+pne_status cond_est(int64_t m, int64_t n, const double* dA, int64_t lda, float* dkappa0,
+                    int32_t* dchoice, void* dwork, size_t work_bytes, pne_stream_t stream);
+
+/* pne_sketch: the sketch step alone, A_s = Omega A (s x n, FP64 output,
+ * ldas >= s) in precision `prec` (FP64, FP32, FP16, BF16, FP8E4M3), with the
+ * operand rounding the solvers use.  Omega as in pne_solve.
+ * Workspace: pne_sketch_workspace_size. */
+size_t pne_sketch_workspace_size(int64_t m, int64_t n, int64_t s, int32_t prec);
+pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
+                      uint32_t problem_id, int32_t prec, int32_t block_rows, double* dAs,
+                      int64_t ldas, void* dwork, size_t work_bytes, pne_stream_t stream);
+
+/* Batched PNE/HPNE (many independent problems in one call).
+ * Problem i is A_i (m_i x n_i, lda_i) at dA_base + a_offset_i doubles, b_i at
+ * db_base + b_offset_i, x_i written at dx_base + x_offset_i.  All problems
+ * share the options; problem_id = i for the sketch of member i.  dinfo has
+ * `batch` device int32 words.  hdesc is a host array. */
+typedef struct {
+    int64_t m, n, lda;
+    int64_t a_offset, b_offset, x_offset;
+} pne_problem_desc;
+
+size_t pne_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc,
+                                  const pne_opts* opts, int hpne);
+pne_status pne_solve_batched(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
+                             const double* db_base, double* dx_base, const pne_opts* opts,
+                             int hpne, void* dwork, size_t work_bytes, int32_t* dinfo,
+                             pne_stream_t stream);
+
+/* Phase timing (diagnostics).  pne_profile_enable(1) makes every following
+ * solve record a HIP event on its stream after each phase of the pipeline
+ * (condition estimate, sketch generation / quantisation / product /
+ * reduction, QR, A R_s^{-1}, Gram product, Gram reduction, factorization,
+ * solves, refinement).  Recording never synchronises.  pne_profile_read
+ * waits for the events of the most recent solve and writes the duration of
+ * phase i (milliseconds, -1 if the phase did not run) to ms[i] for
+ * i < max_phases; it returns the number of phases written (or a negative
+ * pne_status).  pne_profile_phase_name(i) names phase i.  Not thread safe;
+ * meant for benchmarks and tests on one stream. */
+int pne_profile_enable(int enable);
+int pne_profile_read(double* ms, int max_phases);
+const char* pne_profile_phase_name(int i);
+
+/* Human-readable name of a status code (static string). */
+const char* pne_status_string(pne_status st);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PNE_H */

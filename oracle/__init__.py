@@ -62,6 +62,7 @@ def lib():
             "oracle_lu_solve": (i32, [i64, P, i64, P, P, P]),
             "oracle_upper_solve": (i32, [i64, P, i64, P, P]),
             "oracle_cond_est": (i32, [i64, i64, P, i64, ctypes.c_double, P, P, P]),
+            "oracle_sketch_entries": (i32, [i64, P, i64, i64, u64, u32, i32, i64, i64, P, P, P, P]),
             "oracle_solve": (i32, [i32, i64, i64, P, i64, P, i64, u64, u32, i32, i32, i64, i32,
                                    ctypes.c_double, P, P, P, P]),
         }
@@ -114,6 +115,22 @@ def sketch(A, s: int, seed: int, prec: str = "fp64", pid: int = 0, block_rows: i
     if rc:
         raise ValueError(f"oracle_sketch failed: {rc}")
     return (As, Aabs) if want_abs else As
+
+
+def sketch_entries(A, s: int, seed: int, rows, cols, prec: str = "fp64", pid: int = 0,
+                   block_rows: int = 128):
+    """Entries (rows[t], cols[t]) of the sketch and of its absolute product."""
+    A = _f64(A)
+    m = A.shape[0]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros(rows.size)
+    out_abs = np.zeros(rows.size)
+    rc = lib().oracle_sketch_entries(m, _ptr(A), m, s, seed, pid, PREC[prec], block_rows, rows.size,
+                                     _ptr(rows), _ptr(cols), _ptr(out), _ptr(out_abs))
+    if rc:
+        raise ValueError(f"oracle_sketch_entries failed: {rc}")
+    return out, out_abs
 
 
 def householder_r(W) -> np.ndarray:

@@ -700,3 +700,57 @@ int oracle_upper_solve(int64_t n, const double* R, int64_t ldr, const double* y,
 {
     return solve_upper(n, R, ldr, y, x);
 }
+
+/* Selected entries (rows[t], cols[t]) of the sketch A_s = Omega A, computed
+ * one by one with the same operand rounding as oracle_sketch (for checks of
+ * very large sketches where the full product is too slow on the CPU). */
+int oracle_sketch_entries(int64_t m, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                          uint32_t pid, int prec, int64_t block_rows, int64_t count,
+                          const int64_t* rows, const int64_t* cols, double* out, double* out_abs)
+{
+    if (m < 1 || s < 1 || lda < m || prec < PREC_FP64 || prec > PREC_FP8) return -1;
+    if (block_rows < 1) block_rows = 128;
+    int blocked = (prec == PREC_FP16 || prec == PREC_FP8);
+    int64_t bs = blocked ? block_rows : m;
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t i = rows[t], j = cols[t];
+        double acc = 0.0, aacc = 0.0;
+        for (int64_t k0 = 0; k0 < m; k0 += bs) {
+            int64_t k1 = (m - k0 < bs) ? m : k0 + bs;
+            double scale = 1.0;
+            if (blocked) {
+                float amax = 0.0f;
+                for (int64_t k = k0; k < k1; ++k) {
+                    float a = fabsf((float)A[IDX(k, j, lda)]);
+                    if (a > amax) amax = a;
+                }
+                if (amax == 0.0f) continue;
+                if (prec == PREC_FP16) {
+                    int E;
+                    frexpf(amax, &E);
+                    scale = ldexp(1.0, (E - 1) - 14);
+                } else {
+                    scale = (double)(amax / 448.0f);
+                }
+            }
+            double p = 0.0, pa = 0.0;
+            for (int64_t k = k0; k < k1; ++k) {
+                double om = to_operand(oracle_omega_entry(seed, pid, i, k), prec);
+                double a;
+                if (!blocked) {
+                    a = to_operand(A[IDX(k, j, lda)], prec);
+                } else {
+                    float tq = (float)A[IDX(k, j, lda)] / (float)scale;
+                    a = (prec == PREC_FP16) ? oracle_round_fp16((double)tq) : oracle_round_e4m3((double)tq);
+                }
+                p += om * a;
+                pa += fabs(om * a);
+            }
+            acc += p * scale;
+            aacc += pa * scale;
+        }
+        out[t] = acc / sqrt((double)s);
+        if (out_abs) out_abs[t] = aacc / sqrt((double)s);
+    }
+    return 0;
+}

@@ -1,0 +1,190 @@
+// Single-precision condition estimate and precision pick (Section 5.1,
+// Algorithm 1 first step).
+//   G = fl32(A)^T fl32(A)       FP32 MFMA SYRK, split over rows of A
+//   ||G||_1                     max column sum of |G| (symmetric, lower stored)
+//   G = L L^T                   FP32 blocked Cholesky; a bad pivot means the
+//                               estimate "overflows" -> kappa0 = +inf
+//   est ~ ||G^{-1}||_1          Hager's method (Hager 1984): x = (1/n) 1,
+//                               at most five rounds of y = G^{-1} x,
+//                               z = G^{-T} sign(y) (sign 0 = +1); stop when
+//                               ||z||_inf <= z^T x, else x = e_j with j the
+//                               first index of max |z_j|; est = ||y||_1
+//   kappa0 = (1/2) log10(||G||_1 est)
+//   pick: FP16 if kappa0 < 4, FP32 if kappa0 <= 8, else FP64.
+// The factor n of the bound kappa(A)^2 <= n ||G||_1 ||G^{-1}||_1 is left out
+// of kappa0 (with it, kappa(A) = 1e2 would select single precision for
+// 400 <= n <= 2000, contrary to the half-precision pick reported in
+// Section 6.4).
+#include "common.h"
+#include "kernels.h"
+#include "trsv_dev.h"
+
+namespace pne {
+
+__device__ __forceinline__ int32_t pick_precision(float k0)
+{
+    if (!(k0 == k0) || isinf(k0)) return PNE_PREC_FP64;
+    if (k0 < 4.0f) return PNE_PREC_FP16;
+    if (k0 <= 8.0f) return PNE_PREC_FP32;
+    return PNE_PREC_FP64;
+}
+
+__global__ void known_kappa_kernel(double known_kappa, float* k0, int32_t* choice)
+{
+    if (threadIdx.x == 0) {
+        const float v = (float)log10(known_kappa);
+        *k0 = v;
+        *choice = pick_precision(v);
+    }
+}
+
+// ||G||_1 from the lower triangle of the symmetric G (column j sums |G(i,j)|
+// for i >= j and |G(j,i)| for i < j).
+__global__ __launch_bounds__(1024) void norm1_sym_kernel(int64_t n, const float* __restrict__ G, int64_t ld,
+                                                          float* __restrict__ out)
+{
+    __shared__ float red[16];
+    float best = 0.0f;
+    for (int64_t j = threadIdx.x; j < n; j += 1024) {
+        float s = 0.0f;
+        for (int64_t i = 0; i < n; ++i) s += fabsf(i >= j ? G[i + j * ld] : G[j + i * ld]);
+        best = fmaxf(best, s);
+    }
+    best = wave_max(best);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = best;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        float b = 0.0f;
+        for (int i = 0; i < 16; ++i) b = fmaxf(b, red[i]);
+        *out = b;
+    }
+}
+
+__global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __restrict__ L, int64_t ld,
+                                                     const float* __restrict__ g1,
+                                                     const int32_t* __restrict__ info,
+                                                     float* __restrict__ k0, int32_t* __restrict__ choice)
+{
+    extern __shared__ unsigned char smem[];
+    float* x = (float*)smem;
+    float* y = x + n;
+    float* z = y + n;
+    __shared__ float redf[16];
+    __shared__ float redz[16], redd[16];
+    __shared__ int64_t redi[16];
+    __shared__ int stop;
+    __shared__ int64_t jmax_sh;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    if (*info != 0) {
+        if (tid == 0) { *k0 = __builtin_inff(); *choice = PNE_PREC_FP64; }
+        return;
+    }
+    for (int64_t i = tid; i < n; i += 1024) x[i] = 1.0f / (float)n;
+    __syncthreads();
+    float est = 0.0f;
+    for (int it = 0; it < 5; ++it) {
+        for (int64_t i = tid; i < n; i += 1024) y[i] = x[i];
+        __syncthreads();
+        wg_trsv<float>(n, L, ld, true, false, false, y);
+        wg_trsv<float>(n, L, ld, false, true, false, y);
+        float s = 0.0f;
+        for (int64_t i = tid; i < n; i += 1024) s += fabsf(y[i]);
+        s = block_sum(s, redf);
+        est = s;
+        for (int64_t i = tid; i < n; i += 1024) z[i] = (y[i] >= 0.0f) ? 1.0f : -1.0f;
+        __syncthreads();
+        wg_trsv<float>(n, L, ld, true, false, false, z);
+        wg_trsv<float>(n, L, ld, false, true, false, z);
+        // ||z||_inf with its first index, and z^T x
+        float zm = -1.0f, ztx = 0.0f;
+        int64_t zi = INT64_MAX;
+        for (int64_t i = tid; i < n; i += 1024) {
+            const float a = fabsf(z[i]);
+            if (a > zm) { zm = a; zi = i; }
+            ztx += z[i] * x[i];
+        }
+        for (int off = 32; off >= 1; off >>= 1) {
+            const float om = __shfl_xor(zm, off, 64);
+            const int64_t oi = __shfl_xor(zi, off, 64);
+            if (om > zm || (om == zm && oi < zi)) { zm = om; zi = oi; }
+            ztx += __shfl_xor(ztx, off, 64);
+        }
+        if (lane == 0) { redz[wid] = zm; redi[wid] = zi; redd[wid] = ztx; }
+        __syncthreads();
+        if (tid == 0) {
+            float bm = redz[0], d = 0.0f;
+            int64_t bi = redi[0];
+            for (int i = 1; i < 16; ++i)
+                if (redz[i] > bm || (redz[i] == bm && redi[i] < bi)) { bm = redz[i]; bi = redi[i]; }
+            for (int i = 0; i < 16; ++i) d += redd[i];
+            stop = (bm <= d);
+            jmax_sh = bi;
+        }
+        __syncthreads();
+        if (stop) break;
+        const int64_t jm = jmax_sh;
+        for (int64_t i = tid; i < n; i += 1024) x[i] = (i == jm) ? 1.0f : 0.0f;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        const float prod = (*g1) * est;
+        float v = __builtin_inff();
+        if (isfinite(prod) && prod > 0.0f) v = 0.5f * log10f(prod);
+        *k0 = v;
+        *choice = pick_precision(v);
+    }
+}
+
+struct CePlan {
+    int64_t splits, kchunk;
+};
+static CePlan ce_plan(int64_t m, int64_t n)
+{
+    CePlan p;
+    plan_splitk(m, gemm_tiles(n, n, 1, 128), &p.splits, &p.kchunk);
+    return p;
+}
+
+size_t condest_workspace_bytes(int64_t m, int64_t n)
+{
+    CePlan p = ce_plan(m, n);
+    Arena ar(nullptr, 0);
+    ar.take<float>((size_t)n * n);              // G / L
+    ar.take<float>((size_t)p.splits * n * n);   // SYRK partials
+    ar.take<float>(4);                          // ||G||_1
+    ar.take<int32_t>(4);                        // info
+    return ar.used;
+}
+
+int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
+                int32_t* dchoice, void* work, size_t work_bytes, hipStream_t st)
+{
+    if (known_kappa > 0.0) {
+        known_kappa_kernel<<<1, 64, 0, st>>>(known_kappa, dk0, dchoice);
+        return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+    }
+    if (work_bytes < condest_workspace_bytes(m, n)) return PNE_EWORKSPACE;
+    if (n > 4096) return PNE_ENOTSUP;
+    CePlan p = ce_plan(m, n);
+    Arena ar(work, work_bytes);
+    float* G = ar.take<float>((size_t)n * n);
+    float* P = ar.take<float>((size_t)p.splits * n * n);
+    float* g1 = ar.take<float>(4);
+    int32_t* info = ar.take<int32_t>(4);
+    zero_i32(1, info, st);
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = m;
+    g.A = A; g.lda = lda; g.transA = 1;
+    g.B = A; g.ldb = lda; g.transB = 0;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.C = G; g.ldc = n;
+    g.lower = 1;
+    g.splits = p.splits; g.kchunk = p.kchunk; g.P = P;
+    gemm_ddf(g, st);
+    norm1_sym_kernel<<<1, 1024, 0, st>>>(n, G, n, g1);
+    cholesky<float>(n, G, n, info, st);
+    hager_kernel<<<1, 1024, 3 * n * sizeof(float), st>>>(n, G, n, g1, info, dk0, dchoice);
+    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+}
+
+}  // namespace pne

@@ -1,0 +1,281 @@
+// Column-major MFMA GEMM for the FP64 (and FP32) contractions of the path:
+// the off-diagonal updates of the blocked A R_s^{-1}, the Gram products
+// A_p^T A_p / A_p^T A with A_p^T b, the trailing updates of the blocked
+// Cholesky, LU and Householder QR, and the FP64 sketch product.
+//
+// C = alpha op(A) op(B) + beta Cin on 128 x BN output tiles (BN = 64 or 128),
+// 256 threads = 2 x 2 waves, MFMA 16x16x4 (v_mfma_f64_16x16x4f64 or
+// v_mfma_f32_16x16x4f32), K staged through LDS 16 deep with the next K tile
+// prefetched into registers.  The MFMA operands are fed swapped (op(B)^T as
+// the instruction's A, op(A)^T as its B) so that lane l owns output rows
+// i = l % 16: consecutive lanes write consecutive addresses of the
+// column-major result.  Output layout of the 16x16 result in lane l,
+// register r: FP32 row 4*(l/16) + r, FP64 row l/16 + 4*r, column l % 16.  Split-K writes fixed partial buffers that a separate
+// kernel reduces in a fixed order.
+#include "common.h"
+#include "kernels.h"
+
+namespace pne {
+
+constexpr int G_BM = 128, G_BK = 16, G_PAD = 16;
+
+template <typename TC>
+__device__ __forceinline__ auto mfma_cm(TC a, TC b,
+                                        typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type c)
+{
+    if constexpr (sizeof(TC) == 8) return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    else return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void lower_tile(int64_t id, int64_t& ti, int64_t& tj)
+{
+    int64_t t = (int64_t)((sqrt(8.0 * (double)id + 1.0) - 1.0) * 0.5);
+    while (t * (t + 1) / 2 > id) --t;
+    while ((t + 1) * (t + 2) / 2 <= id) ++t;
+    ti = t;
+    tj = id - t * (t + 1) / 2;
+}
+
+template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
+__global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
+{
+    typedef typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type VC;
+    constexpr int TN = BN / 32;                // 16-wide MFMA tiles per wave along N
+    constexpr int LDA_S = G_BM + G_PAD, LDB_S = BN + G_PAD;
+    constexpr int BPT = BN / 16;               // B elements per thread per K tile
+    __shared__ TC As[G_BK * LDA_S];
+    __shared__ TC Bs[G_BK * LDB_S];
+    __shared__ TC bsh[G_BK];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int r16 = lane & 15, g4 = lane >> 4;
+
+    int64_t ti, tj;
+    const int64_t tiles_m = (g.M + G_BM - 1) / G_BM;
+    if (g.lower) lower_tile(blockIdx.x, ti, tj);
+    else { ti = blockIdx.x % tiles_m; tj = blockIdx.x / tiles_m; }
+    const int64_t i0 = ti * G_BM, j0 = tj * BN;
+    const int64_t kbeg = PARTIAL ? (int64_t)blockIdx.y * g.kchunk : 0;
+    int64_t kend = PARTIAL ? kbeg + g.kchunk : g.K;
+    if (kend > g.K) kend = g.K;
+
+    const TA* __restrict__ A = (const TA*)g.A;
+    const TB* __restrict__ B = (const TB*)g.B;
+    const double* __restrict__ bv = (const double*)g.bvec;
+    const bool fold = (bv != nullptr) && (tj == 0);
+
+    VC acc[4][TN];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < TN; ++b) acc[a][b] = (VC){0, 0, 0, 0};
+    TC cpart = 0;
+
+    TC ra[8], rb[BPT], rbv = 0;
+    auto gload = [&](int64_t k0) {
+        if (!g.transA) {
+            const int kk = tid >> 4, ib = (tid & 15) * 8;
+            const int64_t k = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t i = i0 + ib + q;
+                ra[q] = (i < g.M && k < kend) ? (TC)A[i + k * g.lda] : (TC)0;
+            }
+        } else {
+            const int ii = tid >> 1, kb = (tid & 1) * 8;
+            const int64_t i = i0 + ii;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t k = k0 + kb + q;
+                ra[q] = (i < g.M && k < kend) ? (TC)A[k + i * g.lda] : (TC)0;
+            }
+        }
+        if (!g.transB) {
+            constexpr int TPC = 256 / BN;  // threads per column
+            const int jj = tid / TPC, kb = (tid % TPC) * BPT;
+            const int64_t j = j0 + jj;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const int64_t k = k0 + kb + q;
+                rb[q] = (j < g.N && k < kend) ? (TC)B[k + j * g.ldb] : (TC)0;
+            }
+        } else {
+            const int kk = tid >> 4, jb = (tid & 15) * BPT;
+            const int64_t k = k0 + kk;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) {
+                const int64_t j = j0 + jb + q;
+                rb[q] = (j < g.N && k < kend) ? (TC)B[j + k * g.ldb] : (TC)0;
+            }
+        }
+        if (fold && tid < G_BK) rbv = (k0 + tid < kend) ? (TC)bv[k0 + tid] : (TC)0;
+    };
+    auto sstore = [&]() {
+        if (!g.transA) {
+            const int kk = tid >> 4, ib = (tid & 15) * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) As[kk * LDA_S + ib + q] = ra[q];
+        } else {
+            const int ii = tid >> 1, kb = (tid & 1) * 8;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) As[(kb + q) * LDA_S + ii] = ra[q];
+        }
+        if (!g.transB) {
+            constexpr int TPC = 256 / BN;
+            const int jj = tid / TPC, kb = (tid % TPC) * BPT;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) Bs[(kb + q) * LDB_S + jj] = rb[q];
+        } else {
+            const int kk = tid >> 4, jb = (tid & 15) * BPT;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) Bs[kk * LDB_S + jb + q] = rb[q];
+        }
+        if (fold && tid < G_BK) bsh[tid] = rbv;
+    };
+
+    if (kbeg < kend) gload(kbeg);
+    for (int64_t k0 = kbeg; k0 < kend; k0 += G_BK) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (k0 + G_BK < kend) gload(k0 + G_BK);
+#pragma unroll
+        for (int kk = 0; kk < G_BK; kk += 4) {
+            TC fa[4], fb[TN];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) fa[t] = As[(kk + g4) * LDA_S + wm * 64 + t * 16 + r16];
+#pragma unroll
+            for (int t = 0; t < TN; ++t) fb[t] = Bs[(kk + g4) * LDB_S + wn * (BN / 2) + t * 16 + r16];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b) acc[a][b] = mfma_cm<TC>(fb[b], fa[a], acc[a][b]);
+        }
+        if (fold && tid < G_BM) {
+#pragma unroll
+            for (int kk = 0; kk < G_BK; ++kk) cpart += As[kk * LDA_S + tid] * bsh[kk];
+        }
+    }
+
+    // epilogue: lane owns rows i = .. + r16; accumulator register r holds
+    // column j = .. + 4*g4 + r for the FP32 MFMA and j = .. + g4 + 4*r for the
+    // FP64 MFMA (their 16x16 output layouts differ)
+    TC* C = (TC*)g.C;
+    const TC* Cin = (const TC*)g.Cin;
+    TC* P = PARTIAL ? (TC*)g.P + (int64_t)blockIdx.y * g.M * g.N : nullptr;
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t i = i0 + wm * 64 + a * 16 + r16;
+        if (i >= g.M) continue;
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j = j0 + wn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
+                if (j >= g.N) continue;
+                if (PARTIAL) {
+                    TC v = acc[a][b][r];
+                    if (g.accumulate_partials) v += P[i + j * g.M];
+                    P[i + j * g.M] = v;
+                } else {
+                    TC v = (TC)g.alpha * acc[a][b][r];
+                    if (Cin) v += (TC)g.beta * Cin[i + j * g.ldcin];
+                    C[i + j * g.ldc] = v;
+                }
+            }
+    }
+    if (fold && tid < G_BM && i0 + tid < g.M) {
+        if (PARTIAL) ((TC*)g.Pc)[(int64_t)blockIdx.y * g.M + i0 + tid] = cpart;
+        else ((TC*)g.cvec)[i0 + tid] = cpart;
+    }
+}
+
+template <typename TC>
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int bn)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const TC* P = (const TC*)g.P;
+    if (idx < g.M * g.N) {
+        const int64_t i = idx % g.M, j = idx / g.M;
+        if (!g.lower || (i / G_BM) >= (j / bn)) {
+            TC s = 0;
+            for (int64_t z = 0; z < g.splits; ++z) s += P[z * g.M * g.N + idx];
+            TC v = (TC)g.alpha * s;
+            if (g.Cin) v += (TC)g.beta * ((const TC*)g.Cin)[i + j * g.ldcin];
+            ((TC*)g.C)[i + j * g.ldc] = v;
+        }
+    }
+    if (g.bvec && idx < g.M) {
+        TC s = 0;
+        for (int64_t z = 0; z < g.splits; ++z) s += ((const TC*)g.Pc)[z * g.M + idx];
+        ((TC*)g.cvec)[idx] = s;
+    }
+}
+
+int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn)
+{
+    const int64_t tm = ceil_div(M, G_BM), tn = ceil_div(N, bn);
+    if (lower) return tm * (tm + 1) / 2;  // requires bn == G_BM and square problems
+    return tm * tn;
+}
+
+void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk)
+{
+    int64_t want = ceil_div(1024, tiles < 1 ? 1 : tiles);
+    int64_t maxs = K / 256;
+    if (maxs < 1) maxs = 1;
+    int64_t s = want < maxs ? want : maxs;
+    if (s < 1) s = 1;
+    int64_t kc = ceil_div(ceil_div(K, s), G_BK) * G_BK;
+    *kchunk = kc;
+    *splits = ceil_div(K, kc);
+}
+
+template <typename TA, typename TB, typename TC>
+static void gemm_launch(const GemmArgs& g0, hipStream_t st, bool reduce)
+{
+    GemmArgs g = g0;
+    const bool narrow = !g.lower && g.N <= 64;
+    const int bn = narrow ? 64 : 128;
+    const int64_t tiles = gemm_tiles(g.M, g.N, g.lower, bn);
+    if (tiles == 0) return;
+    const bool partial = g.splits > 1 || !reduce;
+    if (!partial) {
+        g.splits = 1;
+        dim3 grid(tiles, 1);
+        if (narrow) gemm_cm_kernel<TA, TB, TC, 64, false><<<grid, 256, 0, st>>>(g);
+        else gemm_cm_kernel<TA, TB, TC, 128, false><<<grid, 256, 0, st>>>(g);
+        return;
+    }
+    if (g.splits < 1) g.splits = 1;
+    if (g.kchunk <= 0) g.kchunk = ceil_div(ceil_div(g.K, g.splits), G_BK) * G_BK;
+    dim3 grid(tiles, g.splits);
+    if (narrow) gemm_cm_kernel<TA, TB, TC, 64, true><<<grid, 256, 0, st>>>(g);
+    else gemm_cm_kernel<TA, TB, TC, 128, true><<<grid, 256, 0, st>>>(g);
+    if (reduce) {
+        int64_t cnt = g.M * g.N;
+        if (g.bvec && g.M > cnt) cnt = g.M;
+        gemm_reduce_kernel<TC><<<ceil_div(cnt, 256), 256, 0, st>>>(g, bn);
+    }
+}
+
+void gemm_f64(const GemmArgs& g, hipStream_t st) { gemm_launch<double, double, double>(g, st, true); }
+void gemm_f64_reduce(const GemmArgs& g, hipStream_t st)
+{
+    int64_t cnt = g.M * g.N;
+    if (g.bvec && g.M > cnt) cnt = g.M;
+    gemm_reduce_kernel<double><<<ceil_div(cnt, 256), 256, 0, st>>>(g, 128);
+}
+void gemm_f64_partials(const GemmArgs& g, hipStream_t st)
+{
+    gemm_launch<double, double, double>(g, st, false);
+}
+void gemm_f32(const GemmArgs& g, hipStream_t st) { gemm_launch<float, float, float>(g, st, true); }
+void gemm_f32_partials(const GemmArgs& g, hipStream_t st)
+{
+    gemm_launch<float, float, float>(g, st, false);
+}
+void gemm_ddf(const GemmArgs& g, hipStream_t st) { gemm_launch<double, double, float>(g, st, true); }
+
+}  // namespace pne

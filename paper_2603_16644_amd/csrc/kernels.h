@@ -1,0 +1,127 @@
+// Internal host-side interfaces between the kernel files and the C ABI layer.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "common.h"
+
+namespace pne {
+
+// Operand kinds of the sketch product.
+enum { OPK_F64 = 0, OPK_F32 = 1, OPK_BF16 = 2, OPK_F16 = 3, OPK_FP8 = 4 };
+
+inline int prec_to_opk(int prec)
+{
+    switch (prec) {
+    case PNE_PREC_FP64: return OPK_F64;
+    case PNE_PREC_FP32: return OPK_F32;
+    case PNE_PREC_BF16: return OPK_BF16;
+    case PNE_PREC_FP16: return OPK_F16;
+    default: return OPK_FP8;
+    }
+}
+inline int64_t opk_bytes(int op)
+{
+    switch (op) {
+    case OPK_F64: return 8;
+    case OPK_F32: return 4;
+    case OPK_BF16:
+    case OPK_F16: return 2;
+    default: return 1;
+    }
+}
+
+// ---------------------------------------------------------------- sketch
+struct SketchPlan {
+    int op;
+    int64_t chunk, nchunks, ldk, splits, kchunk;
+    size_t bytes;
+};
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br);
+size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br);
+int sketch_run(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+               uint32_t pid, int prec, int64_t br, float* As32, int64_t ld32, double* As64,
+               int64_t ld64, void* work, size_t work_bytes, hipStream_t st);
+
+// ---------------------------------------------------------------- GEMM
+// Column-major C = alpha op(A) op(B) + beta Cin (C may alias Cin).
+// With splits > 1 the raw products go to partial buffers P[z] (M x N, ld M)
+// and gemm_reduce_* forms C.  `lower` restricts work to output tiles on or
+// below the diagonal (square 128 x 128 tiles).  With bvec != null the
+// work-groups of the first tile column also form op(A) bvec into Pc[z]
+// (n-vector partials), reduced into cvec.
+struct GemmArgs {
+    int64_t M, N, K;
+    const void* A; int64_t lda; int transA;
+    const void* B; int64_t ldb; int transB;
+    double alpha, beta;
+    const void* Cin; int64_t ldcin;
+    void* C; int64_t ldc;
+    int lower;
+    int64_t splits, kchunk;
+    void* P; int accumulate_partials;
+    const void* bvec; void* Pc; void* cvec;
+};
+// element types: d = double, f = float; "ddf" = A, B stored double, computed in float
+void gemm_f64(const GemmArgs& g, hipStream_t st);           // full path incl. reduce
+void gemm_f64_partials(const GemmArgs& g, hipStream_t st);  // partials only (no reduce)
+void gemm_f64_reduce(const GemmArgs& g, hipStream_t st);    // reduce of the partials (bn = 128)
+void gemm_f32(const GemmArgs& g, hipStream_t st);
+void gemm_f32_partials(const GemmArgs& g, hipStream_t st);
+void gemm_ddf(const GemmArgs& g, hipStream_t st);           // fl32(A)^T fl32(B) etc.
+// split-K plan: splits and kchunk for a long-K product with `tiles` output tiles
+void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk);
+int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn);
+
+// ---------------------------------------------------------------- TRSM / factorizations
+// Ap = A R^{-1}, R upper n x n (FP64), blocked substitution.
+void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
+                      int64_t ldr, double* Ap, int64_t ldap, hipStream_t st);
+// row-parallel substitution on a block of <= 64 columns: X := X R^{-1}
+// (R upper, TL = false) or X := X L^{-T} (L lower, TL = true); element
+// (i, c) of X at X[i*rs + c*cs]; UNIT: unit diagonal
+template <typename T, bool TL, bool UNIT>
+void trsm_leaf(int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr, hipStream_t st);
+// Cholesky (lower, in place) of the n x n matrix C; info word gets 2000+k.
+template <typename T>
+void cholesky(int64_t n, T* C, int64_t ldc, int32_t* info, hipStream_t st);
+// LU with partial pivoting in place; piv 0-based; info 3000+k.
+void lu_factor(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, hipStream_t st);
+// Householder QR (R only) of the s x n matrix W (in place); R (FP64, n x n,
+// upper, ldr) rounded to qr_prec; info 1000+k for a zero diagonal.
+size_t qr_workspace_bytes(int64_t s, int64_t n, int prec);
+int qr_r(int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr, int32_t* info,
+         void* work, size_t work_bytes, hipStream_t st);
+bool qr_supported(int64_t s, int prec);
+
+// ---------------------------------------------------------------- vectors
+// triangular solve with one work-group: x := op(T)^{-1} x
+// uplo: 0 lower, 1 upper; trans: 0 T, 1 T^T; unit: unit diagonal
+template <typename T>
+void trsv(int64_t n, const T* M, int64_t ld, int uplo, int trans, int unit, T* x, hipStream_t st);
+void lu_solve(int64_t n, const double* LU, int64_t ld, const int32_t* piv, double* x, hipStream_t st);
+// x = U^{-1} L^{-1} P c  (c and x may alias)
+void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* c, double* x,
+               hipStream_t st);
+// x = R^{-1} L^{-T} L^{-1} c  (PNE: Cholesky factor L, preconditioner R)
+void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* R, int64_t ldr, const double* c,
+                double* x, hipStream_t st);
+bool lu_supported(int64_t n);
+// r = b - A x
+void residual(int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,
+              double* r, hipStream_t st);
+// y = X^T v (X m x n), split over m with partials P (splits x n)
+size_t gemv_t_partials(int64_t m, int64_t n);
+void gemv_t(int64_t m, int64_t n, const double* X, int64_t ldx, const double* v, double* y,
+            double* P, hipStream_t st);
+void axpy_update(int64_t n, double* x, const double* d, hipStream_t st);   // x += d
+void fill_nan_on_info(int64_t n, double* x, const int32_t* info, hipStream_t st);
+void copy_f64(int64_t n, const double* src, double* dst, hipStream_t st);
+void zero_i32(int64_t n, int32_t* p, hipStream_t st);
+
+// ---------------------------------------------------------------- condition estimate
+size_t condest_workspace_bytes(int64_t m, int64_t n);
+int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
+                int32_t* dchoice, void* work, size_t work_bytes, hipStream_t st);
+
+}  // namespace pne

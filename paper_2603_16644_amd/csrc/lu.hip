@@ -1,0 +1,178 @@
+// LU factorization with partial pivoting P C = L U of the n x n HPNE matrix
+// A_p^T A (Section 1, eq. e_hpne; the system is non-symmetric).  Blocked,
+// right-looking:
+//   panel (PW columns, all rows below): one 512-thread work-group with the
+//     panel in registers; per column the pivot is the first row of largest
+//     magnitude (wavefront argmax, ties to the smaller index), the two rows
+//     are exchanged through LDS, the column is scaled and the rest of the
+//     panel gets the rank-1 update;
+//   the same row exchanges are applied to the other columns;
+//   U12 := L11^{-1} C12 (unit lower, row-parallel leaf on U12^T);
+//   C22 -= L21 U12 (MFMA GEMM).
+// A zero pivot at global column k sets *info = 3000 + k + 1 (first only).
+#include "common.h"
+#include "kernels.h"
+
+namespace pne {
+
+constexpr int LU_THREADS = 512;
+constexpr int LU_WAVES = LU_THREADS / 64;
+
+template <int RPT, int PW>
+__global__ __launch_bounds__(LU_THREADS) void lu_panel_kernel(int64_t h, int w, double* __restrict__ P,
+                                                        int64_t ldc, int32_t* __restrict__ piv,
+                                                        int64_t c0, int32_t* __restrict__ info)
+{
+    __shared__ double rowK[PW], rowP[PW];
+    __shared__ double wv[LU_WAVES];
+    __shared__ int64_t wi[LU_WAVES];
+    __shared__ int64_t pivsh;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    double x[RPT][PW];
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + LU_THREADS * q;
+#pragma unroll
+        for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
+    }
+    for (int k = 0; k < w; ++k) {
+        // argmax |x(r, k)| over r >= k, first index on ties
+        double best = -1.0;
+        int64_t bidx = INT64_MAX;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int64_t r = tid + LU_THREADS * q;
+            double v = -1.0;
+#pragma unroll
+            for (int c = 0; c < PW; ++c)
+                if (c == k) v = fabs(x[q][c]);
+            if (r >= k && r < h && v > best) { best = v; bidx = r; }
+        }
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) {
+            const double ov = __shfl_xor(best, off, 64);
+            const int64_t oi = __shfl_xor(bidx, off, 64);
+            if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
+        }
+        if (lane == 0) { wv[wid] = best; wi[wid] = bidx; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = wv[0];
+            int64_t bi = wi[0];
+            for (int i = 1; i < LU_WAVES; ++i)
+                if (wv[i] > b || (wv[i] == b && wi[i] < bi)) { b = wv[i]; bi = wi[i]; }
+            pivsh = bi;
+            piv[c0 + k] = (int32_t)(c0 + bi);
+        }
+        __syncthreads();
+        const int64_t p = pivsh;
+        // exchange rows k and p of the panel
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int64_t r = tid + LU_THREADS * q;
+            if (r == p)
+#pragma unroll
+                for (int c = 0; c < PW; ++c) rowP[c] = x[q][c];
+            if (r == k)
+#pragma unroll
+                for (int c = 0; c < PW; ++c) rowK[c] = x[q][c];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int64_t r = tid + LU_THREADS * q;
+            if (r == k && p != k)
+#pragma unroll
+                for (int c = 0; c < PW; ++c) x[q][c] = rowP[c];
+            if (r == p && p != k)
+#pragma unroll
+                for (int c = 0; c < PW; ++c) x[q][c] = rowK[c];
+        }
+        double pv = 0.0;
+#pragma unroll
+        for (int c = 0; c < PW; ++c)
+            if (c == k) pv = rowP[c];
+        if (pv == 0.0) {
+            if (tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
+        } else {
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t r = tid + LU_THREADS * q;
+                if (r > k && r < h) {
+                    double l = 0.0;
+#pragma unroll
+                    for (int c = 0; c < PW; ++c)
+                        if (c == k) { l = x[q][c] / pv; x[q][c] = l; }
+#pragma unroll
+                    for (int c = 0; c < PW; ++c)
+                        if (c > k) x[q][c] -= l * rowP[c];
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + LU_THREADS * q;
+        if (r < h)
+#pragma unroll
+            for (int c = 0; c < PW; ++c)
+                if (c < w) P[r + c * ldc] = x[q][c];
+    }
+}
+
+// Apply the panel's row exchanges to every column outside [c0, c0 + w).
+__global__ __launch_bounds__(256) void lu_swap_kernel(int64_t n, double* __restrict__ C, int64_t ldc,
+                                                      const int32_t* __restrict__ piv, int64_t c0,
+                                                      int w)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= n || (j >= c0 && j < c0 + w)) return;
+    double* col = C + j * ldc;
+    for (int k = 0; k < w; ++k) {
+        const int64_t p = piv[c0 + k];
+        const int64_t r = c0 + k;
+        if (p != r) { double t = col[r]; col[r] = col[p]; col[p] = t; }
+    }
+}
+
+template <int RPT, int PW>
+static void lu_steps(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, int64_t c0,
+                     hipStream_t st)
+{
+    const int w = (int)((n - c0 < PW) ? n - c0 : PW);
+    const int64_t h = n - c0;
+    lu_panel_kernel<RPT, PW><<<1, LU_THREADS, 0, st>>>(h, w, C + c0 + c0 * ldc, ldc, piv, c0, info);
+    lu_swap_kernel<<<ceil_div(n, 256), 256, 0, st>>>(n, C, ldc, piv, c0, w);
+    const int64_t rem = n - c0 - w;
+    if (rem <= 0) return;
+    double* C12 = C + c0 + (c0 + w) * ldc;
+    // U12^T L11^T = C12^T: row j of U12^T is column j of C12 (stride 1 along
+    // the row, ldc between rows)
+    trsm_leaf<double, true, true>(rem, w, C12, ldc, 1, C + c0 + c0 * ldc, ldc, st);
+    GemmArgs g{};
+    g.M = rem; g.N = rem; g.K = w;
+    g.A = C + (c0 + w) + c0 * ldc; g.lda = ldc; g.transA = 0;
+    g.B = C12; g.ldb = ldc; g.transB = 0;
+    g.alpha = -1.0; g.beta = 1.0;
+    double* C22 = C + (c0 + w) + (c0 + w) * ldc;
+    g.Cin = C22; g.ldcin = ldc; g.C = C22; g.ldc = ldc;
+    g.splits = 1;
+    gemm_f64(g, st);
+}
+
+bool lu_supported(int64_t n) { return n <= 4096; }
+
+void lu_factor(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, hipStream_t st)
+{
+    int64_t c0 = 0;
+    while (c0 < n) {
+        const int64_t h = n - c0;
+        if (h <= 512) { lu_steps<1, 32>(n, C, ldc, piv, info, c0, st); c0 += 32; }
+        else if (h <= 1024) { lu_steps<2, 32>(n, C, ldc, piv, info, c0, st); c0 += 32; }
+        else if (h <= 2048) { lu_steps<4, 16>(n, C, ldc, piv, info, c0, st); c0 += 16; }
+        else { lu_steps<8, 8>(n, C, ldc, piv, info, c0, st); c0 += 8; }
+    }
+}
+
+}  // namespace pne

@@ -1,0 +1,427 @@
+// Sketch A_s = Omega A (Algorithm 1, "Sketch"; Section 5.2), Omega an
+// s x m Gaussian matrix with N(0, 1/s) entries drawn from the counter-based
+// generator in philox.h.
+//
+// Pipeline per chunk of rows of A (bounded workspace for any m):
+//   1. omega_gen: Omega(:, chunk) written once in the operand format, row
+//      major (each sketch row contiguous over the chunk, zero padded to a
+//      multiple of 64 columns).  VALU bound; every entry is drawn once.
+//   2. quantize:  A(chunk, :) converted to the operand format, column major
+//      (k contiguous), with per-(block, column) scales for FP16/FP8.
+//   3. gemm_lp:   partial A_s += Omega_q A_q on MFMA 16x16 tiles with FP32
+//      accumulation, split over K (rows of A) into fixed partial buffers.
+// A final reduction sums the partials in a fixed order (bitwise
+// reproducible) and applies 1/sqrt(s).
+//
+// Operand rounding (identical in the CPU reference): FP64 inputs go to FP32
+// first, then RNE to BF16/FP16/E4M3.  FP16 uses power-of-two scales
+// 2^(floor(log2 amax) - 14) per block of A, FP8 uses amax / 448 (FP32).
+#include "common.h"
+#include "convert.h"
+#include "kernels.h"
+#include "philox.h"
+#include "profile.h"
+
+namespace pne {
+
+template <int OP>
+struct Op;
+template <>
+struct Op<OPK_F32> {
+    typedef float T;
+    static constexpr int KI = 4;   // K per MFMA
+    static constexpr int EPL = 1;  // operand elements per lane
+};
+template <>
+struct Op<OPK_BF16> {
+    typedef uint16_t T;
+    static constexpr int KI = 32;
+    static constexpr int EPL = 8;
+};
+template <>
+struct Op<OPK_F16> {
+    typedef uint16_t T;
+    static constexpr int KI = 32;
+    static constexpr int EPL = 8;
+};
+template <>
+struct Op<OPK_FP8> {
+    typedef uint8_t T;
+    static constexpr int KI = 32;
+    static constexpr int EPL = 8;
+};
+template <>
+struct Op<OPK_F64> {
+    typedef double T;
+    static constexpr int KI = 4;
+    static constexpr int EPL = 1;
+};
+
+template <int OP>
+__device__ __forceinline__ typename Op<OP>::T to_op(float x)
+{
+    if constexpr (OP == OPK_F32) return x;
+    else if constexpr (OP == OPK_BF16) return f32_to_bf16_bits(x);
+    else if constexpr (OP == OPK_F16) return f32_to_f16_bits(x);
+    else if constexpr (OP == OPK_FP8) return f32_to_e4m3_bits(x);
+    else return (double)x;
+}
+
+// ---------------------------------------------------------------- 1. Omega
+// out[i * ldk + k] = Omega(i, k0 + k) in the operand format, i < s, k < kc;
+// zero for kc <= k < ldk.
+template <int OP>
+__global__ __launch_bounds__(256) void omega_gen_kernel(uint64_t seed, uint32_t pid, int64_t s,
+                                                        int64_t k0, int64_t kc, int64_t ldk,
+                                                        typename Op<OP>::T* __restrict__ out)
+{
+    typedef typename Op<OP>::T T;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t q = blockIdx.y;
+    if (k >= ldk) return;
+    T v[4];
+    if (k < kc) {
+        Gauss4 g = omega_quad(seed, pid, (uint32_t)q, (uint32_t)(k0 + k));
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = to_op<OP>(g.z[t]);
+    } else {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) v[t] = (T)0;
+    }
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int64_t i = 4 * q + t;
+        if (i < s) out[i * ldk + k] = v[t];
+    }
+}
+
+// ---------------------------------------------------------------- 2. quantize A
+// Unscaled formats: Aq[j * ldk + k] = op(A(k0 + k, j)); zero padding.
+template <int OP>
+__global__ __launch_bounds__(256) void quantize_plain_kernel(const double* __restrict__ A,
+                                                             int64_t lda, int64_t k0, int64_t kc,
+                                                             int64_t ldk,
+                                                             typename Op<OP>::T* __restrict__ Aq)
+{
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t j = blockIdx.y;
+    if (k >= ldk) return;
+    float a = (k < kc) ? (float)A[(k0 + k) + j * lda] : 0.0f;
+    Aq[j * ldk + k] = to_op<OP>(a);
+}
+
+// Block-scaled formats: one work-group per (block of `br` rows, column j).
+template <int OP>
+__global__ __launch_bounds__(256) void quantize_scaled_kernel(const double* __restrict__ A,
+                                                              int64_t lda, int64_t k0, int64_t kc,
+                                                              int64_t ldk, int64_t br, int64_t n,
+                                                              typename Op<OP>::T* __restrict__ Aq,
+                                                              float* __restrict__ sc)
+{
+    __shared__ float red[4];
+    const int64_t kb = blockIdx.x, j = blockIdx.y;
+    const int64_t r0 = kb * br;
+    float amax = 0.0f;
+    for (int64_t r = r0 + threadIdx.x; r < r0 + br && r < kc; r += 256)
+        amax = fmaxf(amax, fabsf((float)A[(k0 + r) + j * lda]));
+    amax = wave_max(amax);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+    float scale;
+    if (amax == 0.0f) {
+        scale = 0.0f;
+    } else if constexpr (OP == OPK_F16) {
+        int E;
+        frexpf(amax, &E);                   // amax = f 2^E, f in [0.5, 1)
+        scale = ldexpf(1.0f, (E - 1) - 14);
+    } else {
+        scale = amax / 448.0f;
+    }
+    if (threadIdx.x == 0) sc[kb * n + j] = scale;
+    for (int64_t r = r0 + threadIdx.x; r < r0 + br && r < ldk; r += 256) {
+        float t = 0.0f;
+        if (r < kc && scale != 0.0f) t = (float)A[(k0 + r) + j * lda] / scale;
+        Aq[j * ldk + r] = to_op<OP>(t);
+    }
+}
+
+// ---------------------------------------------------------------- 3. MFMA product
+// P[i + j*M] (+)= sum_{k in split} Om[i*ldk + k] * Aq[j*ldk + k]  (per scale
+// block multiplied by sc[kb*N + j] when SCALED).  128 x 128 output tile per
+// work-group, 4 waves of 64 x 64, MFMA 16x16.  The MFMA A operand is the A
+// side (columns j) and the B operand the Omega side (rows i), so lane l holds
+// output rows i = l % 16 (contiguous in the column-major result).
+constexpr int LP_BM = 128, LP_BN = 128, LP_BK = 64;
+
+template <int OP>
+__device__ __forceinline__ v4f mfma16(const typename Op<OP>::T* a, const typename Op<OP>::T* b,
+                                      v4f c)
+{
+    if constexpr (OP == OPK_F32) {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(*a, *b, c, 0, 0, 0);
+    } else if constexpr (OP == OPK_BF16) {
+        v8bf av = *(const v8bf*)a, bv = *(const v8bf*)b;
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, c, 0, 0, 0);
+    } else if constexpr (OP == OPK_F16) {
+        v8h av = *(const v8h*)a, bv = *(const v8h*)b;
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(av, bv, c, 0, 0, 0);
+    } else {
+        long av = *(const long*)a, bv = *(const long*)b;
+        return __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, c, 0, 0, 0);
+    }
+}
+
+template <int OP, bool SCALED>
+__global__ __launch_bounds__(256) void gemm_lp_kernel(const typename Op<OP>::T* __restrict__ Om,
+                                                      const typename Op<OP>::T* __restrict__ Aq,
+                                                      int64_t ldk, int64_t M, int64_t N,
+                                                      const float* __restrict__ sc, int64_t br,
+                                                      float* __restrict__ P, int64_t kchunk,
+                                                      int accumulate)
+{
+    typedef typename Op<OP>::T T;
+    constexpr int E = sizeof(T);
+    constexpr int PADE = 16 / E;                 // 16 bytes of padding per LDS row
+    constexpr int LDR = LP_BK + PADE;            // LDS row length in elements
+    constexpr int VPR = LP_BK * E / 16;          // 16-byte vectors per tile row
+    constexpr int VPT = LP_BM * VPR / 256;       // vectors per thread per tile
+    __shared__ __attribute__((aligned(16))) T As[LP_BM * LDR];
+    __shared__ __attribute__((aligned(16))) T Bs[LP_BN * LDR];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t tiles_m = (M + LP_BM - 1) / LP_BM;
+    const int64_t i0 = (int64_t)(blockIdx.x % tiles_m) * LP_BM;
+    const int64_t j0 = (int64_t)(blockIdx.x / tiles_m) * LP_BN;
+    const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+    const int64_t kend = (kbeg + kchunk < ldk) ? kbeg + kchunk : ldk;
+
+    v4f acc[4][4], tmp[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            acc[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+            tmp[a][b] = (v4f){0.f, 0.f, 0.f, 0.f};
+        }
+
+    uint4 ra[VPT], rb[VPT];
+    auto gload = [&](int64_t k) {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + 256 * q;
+            const int row = v / VPR, c = v % VPR;
+            const int64_t gi = i0 + row, gj = j0 + row;
+            const int64_t koff = k + (int64_t)c * (16 / E);
+            ra[q] = (gi < M) ? *(const uint4*)(Om + gi * ldk + koff) : make_uint4(0, 0, 0, 0);
+            rb[q] = (gj < N) ? *(const uint4*)(Aq + gj * ldk + koff) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto sstore = [&]() {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + 256 * q;
+            const int row = v / VPR, c = v % VPR;
+            *(uint4*)(As + row * LDR + c * (16 / E)) = ra[q];
+            *(uint4*)(Bs + row * LDR + c * (16 / E)) = rb[q];
+        }
+    };
+
+    const int r16 = lane & 15, g4 = lane >> 4;
+    int steps_in_block = 0;
+    const int steps_per_block = SCALED ? (int)(br / LP_BK) : 1 << 30;
+    if (kbeg < kend) gload(kbeg);
+    for (int64_t k = kbeg; k < kend; k += LP_BK) {
+        __syncthreads();
+        sstore();
+        __syncthreads();
+        if (k + LP_BK < kend) gload(k + LP_BK);
+#pragma unroll
+        for (int kk = 0; kk < LP_BK; kk += Op<OP>::KI) {
+            const int ko = kk + g4 * Op<OP>::EPL;
+            const T* pa[4];
+            const T* pb[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                pb[t] = As + (wm * 64 + t * 16 + r16) * LDR + ko;   // Omega rows i
+                pa[t] = Bs + (wn * 64 + t * 16 + r16) * LDR + ko;   // A columns j
+            }
+#pragma unroll
+            for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) {
+                    if constexpr (SCALED) tmp[ti][tj] = mfma16<OP>(pa[tj], pb[ti], tmp[ti][tj]);
+                    else acc[ti][tj] = mfma16<OP>(pa[tj], pb[ti], acc[ti][tj]);
+                }
+        }
+        if constexpr (SCALED) {
+            if (++steps_in_block == steps_per_block || k + LP_BK >= kend) {
+                const int64_t kb = k / br;
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t j = j0 + wn * 64 + tj * 16 + 4 * g4 + r;
+                        const float s = (j < N) ? sc[kb * N + j] : 0.0f;
+#pragma unroll
+                        for (int ti = 0; ti < 4; ++ti) {
+                            acc[ti][tj][r] += tmp[ti][tj][r] * s;
+                            tmp[ti][tj][r] = 0.0f;
+                        }
+                    }
+                steps_in_block = 0;
+            }
+        }
+    }
+    float* Pp = P + (int64_t)blockIdx.y * M * N;
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti) {
+        const int64_t i = i0 + wm * 64 + ti * 16 + r16;
+        if (i >= M) continue;
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j = j0 + wn * 64 + tj * 16 + 4 * g4 + r;
+                if (j < N) {
+                    float v = acc[ti][tj][r];
+                    if (accumulate) v += Pp[i + j * M];
+                    Pp[i + j * M] = v;
+                }
+            }
+    }
+}
+
+// ---------------------------------------------------------------- 4. reduction
+// As = scale * sum_split P[split]  (fixed order), written as FP32 and/or FP64.
+template <typename TP>
+__global__ __launch_bounds__(256) void sketch_reduce_kernel(const TP* __restrict__ P, int64_t splits,
+                                                            int64_t M, int64_t N, double scale,
+                                                            float* __restrict__ o32, int64_t ld32,
+                                                            double* __restrict__ o64, int64_t ld64)
+{
+    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (idx >= M * N) return;
+    const int64_t i = idx % M, j = idx / M;
+    TP s = 0;
+    for (int64_t p = 0; p < splits; ++p) s += P[p * M * N + idx];
+    if (o32) o32[i + j * ld32] = (float)(s * (TP)scale);
+    if (o64) o64[i + j * ld64] = (double)s * scale;
+}
+
+// ---------------------------------------------------------------- host driver
+size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
+{
+    SketchPlan p = plan_sketch(m, n, s, prec, br);
+    return p.bytes;
+}
+
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
+{
+    SketchPlan p{};
+    const int op = prec_to_opk(prec);
+    const int64_t E = opk_bytes(op);
+    // rows of A per chunk: keep Omega_q of one chunk below ~1 GiB
+    int64_t max_chunk = ((int64_t)1 << 30) / (E * (s > 0 ? s : 1));
+    int64_t align = (op == OPK_FP8 || op == OPK_F16) ? (br > 64 ? br : 64) : 64;
+    max_chunk = (max_chunk / align) * align;
+    if (max_chunk < align) max_chunk = align;
+    int64_t mpad = ceil_div(m, align) * align;
+    p.chunk = mpad < max_chunk ? mpad : max_chunk;
+    p.nchunks = ceil_div(m, p.chunk);
+    p.ldk = p.chunk;  // multiple of 64
+    // split-K so that tiles x splits fills the machine
+    int64_t tiles = ceil_div(s, LP_BM) * ceil_div(n, LP_BN);
+    if (op == OPK_F64) tiles = ceil_div(s, 128) * ceil_div(n, 128);
+    int64_t want = ceil_div(1024, tiles);
+    int64_t maxsplit = p.ldk / (4 * align);
+    if (maxsplit < 1) maxsplit = 1;
+    p.splits = want < maxsplit ? want : maxsplit;
+    if (p.splits < 1) p.splits = 1;
+    p.kchunk = ceil_div(ceil_div(p.ldk, p.splits), align) * align;
+    p.splits = ceil_div(p.ldk, p.kchunk);
+    p.op = op;
+    Arena ar(nullptr, 0);
+    ar.take<char>((size_t)s * p.ldk * E);                           // Omega_q
+    if (op != OPK_F64) ar.take<char>((size_t)n * p.ldk * E);        // A_q
+    if (op == OPK_FP8 || op == OPK_F16) ar.take<float>((size_t)ceil_div(p.ldk, br) * n);
+    ar.take<char>((size_t)p.splits * s * n * (op == OPK_F64 ? 8 : 4));  // partials
+    p.bytes = ar.used;
+    return p;
+}
+
+template <int OP>
+static void launch_chunk(const SketchPlan& p, const double* A, int64_t lda, int64_t k0, int64_t kc,
+                         int64_t n, int64_t s, uint64_t seed, uint32_t pid, int64_t br, void* Omq,
+                         void* Aq, float* sc, void* P, int accumulate, hipStream_t st)
+{
+    typedef typename Op<OP>::T T;
+    dim3 gg(ceil_div(p.ldk, 256), ceil_div(s, 4));
+    omega_gen_kernel<OP><<<gg, 256, 0, st>>>(seed, pid, s, k0, kc, p.ldk, (T*)Omq);
+    prof_mark(PH_SK_OMEGA, st);
+    if constexpr (OP == OPK_F64) {
+        // C(s x n) = Omega_q (rows contiguous over k) * A(chunk rows)
+        GemmArgs g{};
+        g.M = s; g.N = n; g.K = kc;
+        g.A = Omq; g.lda = p.ldk; g.transA = 1;
+        g.B = A + k0; g.ldb = lda; g.transB = 0;
+        g.splits = p.splits; g.kchunk = p.kchunk;
+        g.P = (double*)P; g.accumulate_partials = accumulate;
+        gemm_f64_partials(g, st);
+    } else {
+        constexpr bool SC = (OP == OPK_FP8 || OP == OPK_F16);
+        if constexpr (SC) {
+            dim3 gq(ceil_div(p.ldk, br), n);
+            quantize_scaled_kernel<OP><<<gq, 256, 0, st>>>(A, lda, k0, kc, p.ldk, br, n, (T*)Aq, sc);
+        } else {
+            dim3 gq(ceil_div(p.ldk, 256), n);
+            quantize_plain_kernel<OP><<<gq, 256, 0, st>>>(A, lda, k0, kc, p.ldk, (T*)Aq);
+        }
+        prof_mark(PH_SK_QUANT, st);
+        dim3 gm(ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits);
+        gemm_lp_kernel<OP, SC><<<gm, 256, 0, st>>>((const T*)Omq, (const T*)Aq, p.ldk, s, n, sc, br,
+                                                   (float*)P, p.kchunk, accumulate);
+    }
+    prof_mark(PH_SK_GEMM, st);
+}
+
+// A_s = Omega A in precision `prec`; writes As32 (ld32) and/or As64 (ld64).
+int sketch_run(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+               uint32_t pid, int prec, int64_t br, float* As32, int64_t ld32, double* As64,
+               int64_t ld64, void* work, size_t work_bytes, hipStream_t st)
+{
+    SketchPlan p = plan_sketch(m, n, s, prec, br);
+    if (work_bytes < p.bytes) return PNE_EWORKSPACE;
+    const int64_t E = opk_bytes(p.op);
+    Arena ar(work, work_bytes);
+    void* Omq = ar.take<char>((size_t)s * p.ldk * E);
+    void* Aq = (p.op != OPK_F64) ? (void*)ar.take<char>((size_t)n * p.ldk * E) : nullptr;
+    float* sc = (p.op == OPK_FP8 || p.op == OPK_F16) ? ar.take<float>((size_t)ceil_div(p.ldk, br) * n)
+                                                      : nullptr;
+    void* P = ar.take<char>((size_t)p.splits * s * n * (p.op == OPK_F64 ? 8 : 4));
+    for (int64_t c = 0; c < p.nchunks; ++c) {
+        const int64_t k0 = c * p.chunk;
+        const int64_t kc = (m - k0 < p.chunk) ? m - k0 : p.chunk;
+        const int acc = c > 0;
+        switch (p.op) {
+        case OPK_F64: launch_chunk<OPK_F64>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        case OPK_F32: launch_chunk<OPK_F32>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        case OPK_BF16: launch_chunk<OPK_BF16>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        case OPK_F16: launch_chunk<OPK_F16>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        case OPK_FP8: launch_chunk<OPK_FP8>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        }
+    }
+    const double scale = 1.0 / sqrt((double)s);
+    dim3 gr(ceil_div(s * n, 256));
+    if (p.op == OPK_F64)
+        sketch_reduce_kernel<double><<<gr, 256, 0, st>>>((const double*)P, p.splits, s, n, scale,
+                                                         As32, ld32, As64, ld64);
+    else
+        sketch_reduce_kernel<float><<<gr, 256, 0, st>>>((const float*)P, p.splits, s, n, scale, As32,
+                                                        ld32, As64, ld64);
+    prof_mark(PH_SK_REDUCE, st);
+    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+}
+
+}  // namespace pne

@@ -1,0 +1,79 @@
+// A_p = A R_s^{-1} in FP64 (Algorithm 1, "Solve A_p = A R_s^{-1}", after
+// R_s is promoted to double).  Blocked right-side substitution over column
+// blocks of 64:
+//   A_p(:, J) = A(:, J) - A_p(:, <J) R(<J, J)     (MFMA GEMM, gemm.hip)
+//   A_p(:, J) := A_p(:, J) R(J, J)^{-1}           (row-parallel substitution)
+// The second step keeps one row per lane in registers and runs the plain
+// forward substitution y_j = (t_j - sum_{k<j} y_k R_kj) / R_jj with the
+// 64 x 64 diagonal block broadcast from LDS.  The same leaf serves the
+// Cholesky panel (X L^T = C, TRANS_LOWER).
+#include "common.h"
+#include "kernels.h"
+
+namespace pne {
+
+constexpr int LEAF = 64;
+
+template <typename T, bool TRANS_LOWER, bool UNIT>
+__global__ __launch_bounds__(256) void trsm_leaf_kernel(int64_t m, int w, T* __restrict__ X,
+                                                        int64_t rs, int64_t cs,
+                                                        const T* __restrict__ Rb, int64_t ldr)
+{
+    __shared__ T Rs[LEAF * LEAF];  // Rs[c * 64 + k] = R(k, c), k <= c
+    for (int e = threadIdx.x; e < LEAF * LEAF; e += 256) {
+        const int c = e / LEAF, k = e % LEAF;
+        T v = 0;
+        if (c < w && k <= c) v = TRANS_LOWER ? Rb[c + (int64_t)k * ldr] : Rb[k + (int64_t)c * ldr];
+        if (UNIT && k == c) v = (T)1;
+        Rs[e] = v;
+    }
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    T x[LEAF];
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c) x[c] = (c < w) ? X[i * rs + c * cs] : (T)0;
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c) {
+        if (c < w) {
+            T acc = x[c];
+#pragma unroll
+            for (int k = 0; k < c; ++k) acc -= x[k] * Rs[c * LEAF + k];
+            x[c] = UNIT ? acc : acc / Rs[c * LEAF + c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < LEAF; ++c)
+        if (c < w) X[i * rs + c * cs] = x[c];
+}
+
+template <typename T, bool TL, bool UNIT>
+void trsm_leaf(int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr, hipStream_t st)
+{
+    if (m <= 0) return;
+    trsm_leaf_kernel<T, TL, UNIT><<<ceil_div(m, 256), 256, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
+}
+template void trsm_leaf<double, true, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
+template void trsm_leaf<float, true, false>(int64_t, int, float*, int64_t, int64_t, const float*, int64_t, hipStream_t);
+template void trsm_leaf<double, true, true>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
+template void trsm_leaf<double, false, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
+
+void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
+                      int64_t ldr, double* Ap, int64_t ldap, hipStream_t st)
+{
+    for (int64_t c0 = 0; c0 < n; c0 += LEAF) {
+        const int w = (int)((n - c0 < LEAF) ? n - c0 : LEAF);
+        GemmArgs g{};
+        g.M = m; g.N = w; g.K = c0;
+        g.A = Ap; g.lda = ldap; g.transA = 0;
+        g.B = R + c0 * ldr; g.ldb = ldr; g.transB = 0;
+        g.alpha = -1.0; g.beta = 1.0;
+        g.Cin = A + c0 * lda; g.ldcin = lda;
+        g.C = Ap + c0 * ldap; g.ldc = ldap;
+        g.splits = 1;
+        gemm_f64(g, st);
+        trsm_leaf<double, false, false>(m, w, Ap + c0 * ldap, 1, ldap, R + c0 + c0 * ldr, ldr, st);
+    }
+}
+
+}  // namespace pne
