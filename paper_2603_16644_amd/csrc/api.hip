@@ -51,6 +51,8 @@ struct Buffers {
     double* d;          // n
     double* r;          // m
     double* gv;         // gemv partials
+    double* dinv1;      // block inverses: Cholesky factor L, or unit lower L of the LU
+    double* dinv2;      // block inverses: R_s (PNE) or U (HPNE)
     float* k0;          // condition estimate
     int32_t* choice;
 };
@@ -97,6 +99,8 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
     b.d = ar.take<double>(p.n);
     b.r = ar.take<double>(p.m);
     b.gv = ar.take<double>(gemv_t_partials(p.m, p.n));
+    b.dinv1 = ar.take<double>(dinv_elems(p.n));
+    b.dinv2 = ar.take<double>(dinv_elems(p.n));
     b.k0 = ar.take<float>(4);
     b.choice = ar.take<int32_t>(4);
     if (out) *out = b;
@@ -217,17 +221,24 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
     prof_mark(PH_GRAM_GEMM, st);
     gemm_f64_reduce(g, st);
     prof_mark(PH_GRAM_REDUCE, st);
-    if (hpne) lu_factor(n, b.C, n, b.piv, dinfo, st);
-    else cholesky<double>(n, b.C, n, dinfo, st);
+    if (hpne) {
+        lu_factor(n, b.C, n, b.piv, dinfo, st);
+        inv_diag_blocks<double>(n, b.C, n, 1, 0, 1, b.dinv1, st);
+        inv_diag_blocks<double>(n, b.C, n, 0, 0, 0, b.dinv2, st);
+    } else {
+        cholesky<double>(n, b.C, n, dinfo, st);
+        inv_diag_blocks<double>(n, b.C, n, 1, 0, 0, b.dinv1, st);
+        inv_diag_blocks<double>(n, b.R, n, 0, 0, 0, b.dinv2, st);
+    }
     prof_mark(PH_FACTOR, st);
-    if (hpne) lu_solve2(n, b.C, n, b.piv, b.c, dx, st);
-    else pne_solve3(n, b.C, n, b.R, n, b.c, dx, st);
+    if (hpne) lu_solve2(n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, st);
+    else pne_solve3(n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.c, dx, st);
     prof_mark(PH_SOLVE, st);
     for (int k = 0; k < p.refine; ++k) {
         residual(m, n, dA, lda, db, dx, b.r, st);
         gemv_t(m, n, b.Ap, m, b.r, b.y, b.gv, st);
-        if (hpne) lu_solve2(n, b.C, n, b.piv, b.y, b.d, st);
-        else pne_solve3(n, b.C, n, b.R, n, b.y, b.d, st);
+        if (hpne) lu_solve2(n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, st);
+        else pne_solve3(n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.y, b.d, st);
         axpy_update(n, dx, b.d, st);
     }
     fill_nan_on_info(n, dx, dinfo, st);

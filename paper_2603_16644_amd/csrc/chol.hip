@@ -13,36 +13,52 @@ namespace pne {
 
 constexpr int CB = 64;
 
+// Unblocked Cholesky of one w x w (w <= 64) diagonal block: lane i of every
+// wave holds row i; wave q holds columns 16q .. 16q+15 in registers.  Step k:
+// the owner wave of column k forms L(:, k) and publishes it in LDS; every wave
+// then updates its columns j > k: L(i, j) -= L(i, k) L(j, k).
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int w, T* __restrict__ C, int64_t ldc,
                                                          int32_t* __restrict__ info, int64_t c0)
 {
-    __shared__ T L[CB * (CB + 1)];
-    const int tid = threadIdx.x;
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e % CB, j = e / CB;
-        L[i + j * (CB + 1)] = (i < w && j < w && i >= j) ? C[i + (int64_t)j * ldc] : (T)0;
+    __shared__ T lcol[CB];
+    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+    T a[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int j = 16 * q + t;
+        a[t] = (lane < w && j < w && lane >= j) ? C[lane + (int64_t)j * ldc] : (T)0;
     }
-    __syncthreads();
     for (int k = 0; k < w; ++k) {
-        T d = L[k + k * (CB + 1)];
-        const bool bad = !(d > (T)0) || !isfinite(d);
-        if (bad && tid == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + k) + 1;
-        const T lkk = bad ? (T)NAN : (T)sqrt(d);
+        const int qk = k >> 4, tk = k & 15;
+        if (q == qk) {
+            T v = 0;
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (t == tk) v = a[t];
+            const T d = __shfl(v, k, 64);
+            const bool bad = !(d > (T)0) || !isfinite(d);
+            if (bad && lane == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + k) + 1;
+            const T lkk = bad ? (T)NAN : (T)sqrt(d);
+            const T l = (lane > k) ? v / lkk : (lane == k ? lkk : (T)0);
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (t == tk) a[t] = l;
+            lcol[lane] = l;
+        }
         __syncthreads();
-        if (tid == 0) L[k + k * (CB + 1)] = lkk;
-        if (tid > k && tid < w) L[tid + k * (CB + 1)] /= lkk;
-        __syncthreads();
-        // trailing update of the lower triangle: L(i, j) -= L(i, k) L(j, k), k < j <= i
-        for (int e = tid; e < CB * CB; e += 256) {
-            const int i = e % CB, j = e / CB;
-            if (j > k && i >= j && i < w) L[i + j * (CB + 1)] -= L[i + k * (CB + 1)] * L[j + k * (CB + 1)];
+        const T li = lcol[lane];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int j = 16 * q + t;
+            if (j > k) a[t] -= li * lcol[j];
         }
         __syncthreads();
     }
-    for (int e = tid; e < CB * CB; e += 256) {
-        const int i = e % CB, j = e / CB;
-        if (i < w && j < w) C[i + (int64_t)j * ldc] = (i >= j) ? L[i + j * (CB + 1)] : (T)0;
+#pragma unroll
+    for (int t = 0; t < 16; ++t) {
+        const int j = 16 * q + t;
+        if (lane < w && j < w) C[lane + (int64_t)j * ldc] = (lane >= j) ? a[t] : (T)0;
     }
 }
 

@@ -5,6 +5,8 @@
 //   G = L L^T                   FP32 blocked Cholesky; a bad pivot means the
 //                               estimate "overflows" -> kappa0 = +inf
 //   est ~ ||G^{-1}||_1          Hager's method (Hager 1984): x = (1/n) 1,
+//                               (solves through the inverted 64 x 64
+//                               diagonal blocks of L),
 //                               at most five rounds of y = G^{-1} x,
 //                               z = G^{-T} sign(y) (sign 0 = +1); stop when
 //                               ||z||_inf <= z^T x, else x = e_j with j the
@@ -61,6 +63,7 @@ __global__ __launch_bounds__(1024) void norm1_sym_kernel(int64_t n, const float*
 }
 
 __global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __restrict__ L, int64_t ld,
+                                                     const float* __restrict__ DL,
                                                      const float* __restrict__ g1,
                                                      const int32_t* __restrict__ info,
                                                      float* __restrict__ k0, int32_t* __restrict__ choice)
@@ -70,6 +73,7 @@ __global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __r
     float* y = x + n;
     float* z = y + n;
     __shared__ float redf[16];
+    __shared__ float tmp[TB];
     __shared__ float redz[16], redd[16];
     __shared__ int64_t redi[16];
     __shared__ int stop;
@@ -85,16 +89,16 @@ __global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __r
     for (int it = 0; it < 5; ++it) {
         for (int64_t i = tid; i < n; i += 1024) y[i] = x[i];
         __syncthreads();
-        wg_trsv<float>(n, L, ld, true, false, false, y);
-        wg_trsv<float>(n, L, ld, false, true, false, y);
+        wg_trsv_inv<float>(n, L, ld, true, false, DL, false, y, tmp);
+        wg_trsv_inv<float>(n, L, ld, false, true, DL, true, y, tmp);
         float s = 0.0f;
         for (int64_t i = tid; i < n; i += 1024) s += fabsf(y[i]);
         s = block_sum(s, redf);
         est = s;
         for (int64_t i = tid; i < n; i += 1024) z[i] = (y[i] >= 0.0f) ? 1.0f : -1.0f;
         __syncthreads();
-        wg_trsv<float>(n, L, ld, true, false, false, z);
-        wg_trsv<float>(n, L, ld, false, true, false, z);
+        wg_trsv_inv<float>(n, L, ld, true, false, DL, false, z, tmp);
+        wg_trsv_inv<float>(n, L, ld, false, true, DL, true, z, tmp);
         // ||z||_inf with its first index, and z^T x
         float zm = -1.0f, ztx = 0.0f;
         int64_t zi = INT64_MAX;
@@ -153,6 +157,7 @@ size_t condest_workspace_bytes(int64_t m, int64_t n)
     ar.take<float>((size_t)p.splits * n * n);   // SYRK partials
     ar.take<float>(4);                          // ||G||_1
     ar.take<int32_t>(4);                        // info
+    ar.take<float>(dinv_elems(n));              // block inverses of L
     return ar.used;
 }
 
@@ -171,6 +176,7 @@ int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known
     float* P = ar.take<float>((size_t)p.splits * n * n);
     float* g1 = ar.take<float>(4);
     int32_t* info = ar.take<int32_t>(4);
+    float* DL = ar.take<float>(dinv_elems(n));
     zero_i32(1, info, st);
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;
@@ -183,7 +189,8 @@ int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known
     gemm_ddf(g, st);
     norm1_sym_kernel<<<1, 1024, 0, st>>>(n, G, n, g1);
     cholesky<float>(n, G, n, info, st);
-    hager_kernel<<<1, 1024, 3 * n * sizeof(float), st>>>(n, G, n, g1, info, dk0, dchoice);
+    inv_diag_blocks<float>(n, G, n, 1, 0, 0, DL, st);
+    hager_kernel<<<1, 1024, 3 * n * sizeof(float), st>>>(n, G, n, DL, g1, info, dk0, dchoice);
     return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
 }
 

@@ -37,15 +37,16 @@ __device__ __forceinline__ void lower_tile(int64_t id, int64_t& ti, int64_t& tj)
 }
 
 template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
-__global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_cm_kernel(GemmArgs g)
 {
     typedef typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type VC;
     constexpr int TN = BN / 32;                // 16-wide MFMA tiles per wave along N
     constexpr int LDA_S = G_BM + G_PAD, LDB_S = BN + G_PAD;
     constexpr int BPT = BN / 16;               // B elements per thread per K tile
-    __shared__ TC As[G_BK * LDA_S];
-    __shared__ TC Bs[G_BK * LDB_S];
-    __shared__ TC bsh[G_BK];
+    // two LDS buffers: the tile in use and the next one
+    __shared__ TC As[2][G_BK * LDA_S];
+    __shared__ TC Bs[2][G_BK * LDB_S];
+    __shared__ TC bsh[2][G_BK];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
@@ -64,6 +65,9 @@ __global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
     const TB* __restrict__ B = (const TB*)g.B;
     const double* __restrict__ bv = (const double*)g.bvec;
     const bool fold = (bv != nullptr) && (tj == 0);
+    // 16-byte vector loads when every run of 8 (A) / BPT (B) elements is aligned
+    const bool vecA = sizeof(TA) == 8 && ((g.lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
+    const bool vecB = sizeof(TB) == 8 && ((g.ldb & 1) == 0) && (((uintptr_t)B & 15) == 0);
 
     VC acc[4][TN];
 #pragma unroll
@@ -73,80 +77,134 @@ __global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
     TC cpart = 0;
 
     TC ra[8], rb[BPT], rbv = 0;
+    // Load the K tile starting at k0 into registers (zero outside the matrix).
     auto gload = [&](int64_t k0) {
         if (!g.transA) {
             const int kk = tid >> 4, ib = (tid & 15) * 8;
             const int64_t k = k0 + kk;
+            const TA* p = A + (i0 + ib) + k * g.lda;
+            if (vecA && k < kend && i0 + ib + 8 <= g.M) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int64_t i = i0 + ib + q;
-                ra[q] = (i < g.M && k < kend) ? (TC)A[i + k * g.lda] : (TC)0;
+                for (int q = 0; q < 8; q += 2) {
+                    const double2 v = *(const double2*)(p + q);
+                    ra[q] = (TC)v.x; ra[q + 1] = (TC)v.y;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) ra[q] = (i0 + ib + q < g.M && k < kend) ? (TC)p[q] : (TC)0;
             }
         } else {
             const int ii = tid >> 1, kb = (tid & 1) * 8;
             const int64_t i = i0 + ii;
+            const TA* p = A + (k0 + kb) + i * g.lda;
+            if (vecA && i < g.M && k0 + kb + 8 <= kend) {
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                const int64_t k = k0 + kb + q;
-                ra[q] = (i < g.M && k < kend) ? (TC)A[k + i * g.lda] : (TC)0;
+                for (int q = 0; q < 8; q += 2) {
+                    const double2 v = *(const double2*)(p + q);
+                    ra[q] = (TC)v.x; ra[q + 1] = (TC)v.y;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) ra[q] = (i < g.M && k0 + kb + q < kend) ? (TC)p[q] : (TC)0;
             }
         }
         if (!g.transB) {
             constexpr int TPC = 256 / BN;  // threads per column
             const int jj = tid / TPC, kb = (tid % TPC) * BPT;
             const int64_t j = j0 + jj;
+            const TB* p = B + (k0 + kb) + j * g.ldb;
+            if (vecB && j < g.N && k0 + kb + BPT <= kend) {
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) {
-                const int64_t k = k0 + kb + q;
-                rb[q] = (j < g.N && k < kend) ? (TC)B[k + j * g.ldb] : (TC)0;
+                for (int q = 0; q < BPT; q += 2) {
+                    const double2 v = *(const double2*)(p + q);
+                    rb[q] = (TC)v.x; rb[q + 1] = (TC)v.y;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < BPT; ++q) rb[q] = (j < g.N && k0 + kb + q < kend) ? (TC)p[q] : (TC)0;
             }
         } else {
             const int kk = tid >> 4, jb = (tid & 15) * BPT;
             const int64_t k = k0 + kk;
+            const TB* p = B + (j0 + jb) + k * g.ldb;
+            if (vecB && k < kend && j0 + jb + BPT <= g.N) {
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) {
-                const int64_t j = j0 + jb + q;
-                rb[q] = (j < g.N && k < kend) ? (TC)B[j + k * g.ldb] : (TC)0;
+                for (int q = 0; q < BPT; q += 2) {
+                    const double2 v = *(const double2*)(p + q);
+                    rb[q] = (TC)v.x; rb[q + 1] = (TC)v.y;
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < BPT; ++q) rb[q] = (j0 + jb + q < g.N && k < kend) ? (TC)p[q] : (TC)0;
             }
         }
         if (fold && tid < G_BK) rbv = (k0 + tid < kend) ? (TC)bv[k0 + tid] : (TC)0;
     };
-    auto sstore = [&]() {
+    auto sstore = [&](int buf) {
+        TC* as = As[buf];
+        TC* bs = Bs[buf];
         if (!g.transA) {
             const int kk = tid >> 4, ib = (tid & 15) * 8;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) As[kk * LDA_S + ib + q] = ra[q];
+            for (int q = 0; q < 8; ++q) as[kk * LDA_S + ib + q] = ra[q];
         } else {
             const int ii = tid >> 1, kb = (tid & 1) * 8;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) As[(kb + q) * LDA_S + ii] = ra[q];
+            for (int q = 0; q < 8; ++q) as[(kb + q) * LDA_S + ii] = ra[q];
         }
         if (!g.transB) {
             constexpr int TPC = 256 / BN;
             const int jj = tid / TPC, kb = (tid % TPC) * BPT;
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) Bs[(kb + q) * LDB_S + jj] = rb[q];
+            for (int q = 0; q < BPT; ++q) bs[(kb + q) * LDB_S + jj] = rb[q];
         } else {
             const int kk = tid >> 4, jb = (tid & 15) * BPT;
 #pragma unroll
-            for (int q = 0; q < BPT; ++q) Bs[kk * LDB_S + jb + q] = rb[q];
+            for (int q = 0; q < BPT; ++q) bs[kk * LDB_S + jb + q] = rb[q];
         }
-        if (fold && tid < G_BK) bsh[tid] = rbv;
+        if (fold && tid < G_BK) bsh[buf][tid] = rbv;
     };
 
-    if (kbeg < kend) gload(kbeg);
+    // FP32 products with a single K tile (the QR trailing update, K = panel
+    // width): fetch the Cin values of the lane together with the operands.
+    constexpr bool PRE = sizeof(TC) == 4 && !PARTIAL;
+    TC pre[PRE ? 4 : 1][PRE ? TN : 1][PRE ? 4 : 1];
+    const bool use_pre = PRE && g.Cin != nullptr && (kend - kbeg) <= G_BK;
+    if constexpr (PRE) {
+        if (use_pre) {
+            const TC* Cin0 = (const TC*)g.Cin;
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < TN; ++b)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        const int64_t i = i0 + wm * 64 + a * 16 + r16;
+                        const int64_t j = j0 + wn * (BN / 2) + b * 16 + 4 * g4 + r;
+                        pre[a][b][r] = (i < g.M && j < g.N) ? Cin0[i + j * g.ldcin] : (TC)0;
+                    }
+        }
+    }
+
+    // Pipeline: tile t is in LDS buffer t % 2 while tile t + 1 is being
+    // loaded into registers; one barrier per tile.
+    int buf = 0;
+    if (kbeg < kend) {
+        gload(kbeg);
+        sstore(0);
+        if (kbeg + G_BK < kend) gload(kbeg + G_BK);
+    }
     for (int64_t k0 = kbeg; k0 < kend; k0 += G_BK) {
         __syncthreads();
-        sstore();
-        __syncthreads();
-        if (k0 + G_BK < kend) gload(k0 + G_BK);
+        const TC* as = As[buf];
+        const TC* bs = Bs[buf];
 #pragma unroll
         for (int kk = 0; kk < G_BK; kk += 4) {
             TC fa[4], fb[TN];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) fa[t] = As[(kk + g4) * LDA_S + wm * 64 + t * 16 + r16];
+            for (int t = 0; t < 4; ++t) fa[t] = as[(kk + g4) * LDA_S + wm * 64 + t * 16 + r16];
 #pragma unroll
-            for (int t = 0; t < TN; ++t) fb[t] = Bs[(kk + g4) * LDB_S + wn * (BN / 2) + t * 16 + r16];
+            for (int t = 0; t < TN; ++t) fb[t] = bs[(kk + g4) * LDB_S + wn * (BN / 2) + t * 16 + r16];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -154,19 +212,39 @@ __global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
         }
         if (fold && tid < G_BM) {
 #pragma unroll
-            for (int kk = 0; kk < G_BK; ++kk) cpart += As[kk * LDA_S + tid] * bsh[kk];
+            for (int kk = 0; kk < G_BK; ++kk) cpart += as[kk * LDA_S + tid] * bsh[buf][kk];
         }
+        if (k0 + G_BK < kend) {
+            sstore(buf ^ 1);
+            if (k0 + 2 * G_BK < kend) gload(k0 + 2 * G_BK);
+        }
+        buf ^= 1;
     }
 
     // epilogue: lane owns rows i = .. + r16; accumulator register r holds
     // column j = .. + 4*g4 + r for the FP32 MFMA and j = .. + g4 + 4*r for the
-    // FP64 MFMA (their 16x16 output layouts differ)
+    // FP64 MFMA (their 16x16 output layouts differ).  C may alias Cin: per row
+    // tile every Cin value of the lane is loaded before the first store, so
+    // the loads are not serialised behind stores one by one.
     TC* C = (TC*)g.C;
     const TC* Cin = (const TC*)g.Cin;
     TC* P = PARTIAL ? (TC*)g.P + (int64_t)blockIdx.y * g.M * g.N : nullptr;
+    const TC* src = PARTIAL ? (g.accumulate_partials ? P : nullptr) : Cin;
+    const int64_t lds_ = PARTIAL ? g.M : g.ldcin;
 #pragma unroll
     for (int a = 0; a < 4; ++a) {
         const int64_t i = i0 + wm * 64 + a * 16 + r16;
+        TC prev[TN][4];
+#pragma unroll
+        for (int b = 0; b < TN; ++b)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j = j0 + wn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
+                if constexpr (PRE) {
+                    if (use_pre) { prev[b][r] = pre[a][b][r]; continue; }
+                }
+                prev[b][r] = (src && i < g.M && j < g.N) ? src[i + j * lds_] : (TC)0;
+            }
         if (i >= g.M) continue;
 #pragma unroll
         for (int b = 0; b < TN; ++b)
@@ -174,15 +252,8 @@ __global__ __launch_bounds__(256) void gemm_cm_kernel(GemmArgs g)
             for (int r = 0; r < 4; ++r) {
                 const int64_t j = j0 + wn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
                 if (j >= g.N) continue;
-                if (PARTIAL) {
-                    TC v = acc[a][b][r];
-                    if (g.accumulate_partials) v += P[i + j * g.M];
-                    P[i + j * g.M] = v;
-                } else {
-                    TC v = (TC)g.alpha * acc[a][b][r];
-                    if (Cin) v += (TC)g.beta * Cin[i + j * g.ldcin];
-                    C[i + j * g.ldc] = v;
-                }
+                if (PARTIAL) P[i + j * g.M] = acc[a][b][r] + prev[b][r];
+                else C[i + j * g.ldc] = (TC)g.alpha * acc[a][b][r] + (TC)g.beta * prev[b][r];
             }
     }
     if (fold && tid < G_BM && i0 + tid < g.M) {
@@ -223,7 +294,7 @@ int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn)
 void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk)
 {
     int64_t want = ceil_div(1024, tiles < 1 ? 1 : tiles);
-    int64_t maxs = K / 256;
+    int64_t maxs = K / 128;
     if (maxs < 1) maxs = 1;
     int64_t s = want < maxs ? want : maxs;
     if (s < 1) s = 1;

@@ -99,13 +99,18 @@ bool qr_supported(int64_t s, int prec);
 // uplo: 0 lower, 1 upper; trans: 0 T, 1 T^T; unit: unit diagonal
 template <typename T>
 void trsv(int64_t n, const T* M, int64_t ld, int uplo, int trans, int unit, T* x, hipStream_t st);
-void lu_solve(int64_t n, const double* LU, int64_t ld, const int32_t* piv, double* x, hipStream_t st);
-// x = U^{-1} L^{-1} P c  (c and x may alias)
-void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* c, double* x,
-               hipStream_t st);
-// x = R^{-1} L^{-T} L^{-1} c  (PNE: Cholesky factor L, preconditioner R)
-void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* R, int64_t ldr, const double* c,
-                double* x, hipStream_t st);
+// inverses of the 64 x 64 diagonal blocks of op(M) (dinv_elems(n) values)
+size_t dinv_elems(int64_t n);
+template <typename T>
+void inv_diag_blocks(int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv, hipStream_t st);
+// x = U^{-1} L^{-1} P c (c and x may alias); DL, DU: block inverses of the
+// unit lower L and of U
+void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL, const double* DU,
+               const double* c, double* x, hipStream_t st);
+// x = R^{-1} L^{-T} L^{-1} c (PNE: Cholesky factor L, preconditioner R) with
+// the block inverses DL of L and DR of R
+void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* DL, const double* R, int64_t ldr,
+                const double* DR, const double* c, double* x, hipStream_t st);
 bool lu_supported(int64_t n);
 // r = b - A x
 void residual(int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,

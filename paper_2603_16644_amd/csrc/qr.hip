@@ -3,12 +3,12 @@
 // R_s to FP64 (Algorithm 1, "Promote R_s").
 //
 // Blocked compact-WY form (Golub & Van Loan, Section 5.2.3):
-//   panel:  one 512-thread work-group holds the h x NB panel in registers
-//           (thread t owns rows t, t+512, ...) and applies NB reflectors
+//   panel:  one work-group (512 or 1024 threads) holds the h x NB panel in
+//           registers (thread t owns rows t, t+NT, ...) and applies NB reflectors
 //           in the LAPACK convention (beta = -sign(alpha) ||x||); each
-//           column needs one norm reduction and one batched reduction that
-//           delivers both the dot products v^T P(:, j) of the update and the
-//           V^T v column of the triangular factor T (H_1..H_NB = I - V T V^T);
+//           column needs a single batched reduction, which delivers the norm,
+//           the dot products v^T P(:, j) of the update and the V^T v column of
+//           the triangular factor T (H_1..H_NB = I - V T V^T);
 //   update: Y^T = W_trail^T V (MFMA GEMM, split over rows), Z = T^T Y,
 //           W_trail -= V Z (MFMA GEMM).
 // Working precision: FP64 for qr_prec = FP64, FP32 otherwise.  For BF16 and
@@ -26,7 +26,9 @@ __device__ __forceinline__ void batched_block_sum(T (&v)[NB], T (*red)[NB], T* b
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int LOGNB = (NB == 32) ? 5 : (NB == 16 ? 4 : 3);
     // transpose-reduce: each halving step keeps half the entries and adds the
-    // partner lane's copy of them
+    // partner lane's copy of them.  Both candidate sums are formed explicitly
+    // (selecting between array entries with a lane-dependent condition would
+    // be lowered to an indexed access over the whole array).
 #pragma unroll
     for (int step = 0; step < LOGNB; ++step) {
         const int o = 32 >> step;
@@ -34,9 +36,9 @@ __device__ __forceinline__ void batched_block_sum(T (&v)[NB], T (*red)[NB], T* b
         const bool hi = (lane & o) != 0;
 #pragma unroll
         for (int i = 0; i < half; ++i) {
-            const T keep = hi ? v[i + half] : v[i];
-            const T send = hi ? v[i] : v[i + half];
-            v[i] = keep + __shfl_xor(send, o, 64);
+            const T lo_sum = v[i] + __shfl_xor(v[i], o, 64);
+            const T hi_sum = v[i + half] + __shfl_xor(v[i + half], o, 64);
+            v[i] = hi ? hi_sum : lo_sum;
         }
     }
     T s = v[0];
@@ -53,116 +55,142 @@ __device__ __forceinline__ void batched_block_sum(T (&v)[NB], T (*red)[NB], T* b
     __syncthreads();
 }
 
-constexpr int QR_THREADS = 512;
-constexpr int QR_WAVES = QR_THREADS / 64;
 
-template <typename T, int NB, int RPT>
-__global__ __launch_bounds__(QR_THREADS) void qr_panel_kernel(int64_t h, int w, T* __restrict__ W, int64_t ldw,
-                                                        T* __restrict__ V, int64_t ldv,
-                                                        T* __restrict__ Tout)
+// Panel of h rows and w <= NB columns.  For column k one batched reduction
+// over the rows r > k gives
+//   s_c = sum_{r>k} x(r, k) x(r, c)   for every panel column c,
+// i.e. sigma = s_k, the dot products of the trailing columns (c > k) and the
+// products V(:, c)^T x of the earlier reflectors (c < k).  The thread that
+// owns row k then forms (LAPACK convention) beta = -sign(alpha) sqrt(alpha^2
+// + sigma), tau = (beta - alpha) / beta and v = [1; x(r>k) / (alpha - beta)],
+// the coefficients tau v^T P(:, c) = tau (P(k, c) + s_c / (alpha - beta)) of
+// the rank-1 update and the vector V^T v that extends the triangular factor T.
+template <typename T, int NB, int NT>
+struct PanelShared {
+    T red[NT / 64][NB];
+    T bc[NB];
+    T cf[NB];      // tau * v^T P(:, c) for c > k
+    T gv[NB];      // V(:, i)^T v for i < k
+    T sc[2];       // 1 / (alpha - beta), tau
+    T Ts[NB][NB + 1];
+};
+
+// One column step of the panel (see qr_panel_kernel).  KS >= 0 makes the
+// column index a compile-time constant (KS == k); KS < 0 takes k at run time.
+template <typename T, int NB, int RPT, int NT, int KS>
+__device__ __forceinline__ void panel_step(int k_rt, int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
 {
-    __shared__ T red[QR_WAVES][NB];
-    __shared__ T bc[NB];
-    __shared__ T rs[QR_WAVES];
-    __shared__ T sc[3];
-    __shared__ T Ts[NB][NB + 1];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    for (int e = tid; e < NB * NB; e += QR_THREADS) Ts[e / NB][e % NB] = 0;
+    const int k = KS >= 0 ? KS : k_rt;
+    const int tid = threadIdx.x;
+    T vals[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) vals[c] = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + NT * q;
+        T xk = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == k) xk = x[q][c];
+        xk = (r > k) ? xk : (T)0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) vals[c] += xk * x[q][c];
+    }
+    batched_block_sum<T, NB>(vals, sh.red, sh.bc, NT / 64);
+    if (tid == k) {
+        T alpha = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == k) alpha = x[0][c];
+        const T sigma = sh.bc[k];
+        T beta, tau, inv;
+        if (sigma == (T)0) {
+            beta = alpha; tau = 0; inv = 0;
+        } else {
+            const T nrm = sqrt(alpha * alpha + sigma);
+            beta = (alpha >= (T)0) ? -nrm : nrm;
+            tau = (beta - alpha) / beta;
+            inv = (T)1 / (alpha - beta);
+        }
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c > k && c < w) sh.cf[c] = tau * (x[0][c] + sh.bc[c] * inv);
+            if (c < k) sh.gv[c] = x[0][c] + sh.bc[c] * inv;
+            if (c == k) x[0][c] = beta;
+        }
+        sh.sc[0] = inv;
+        sh.sc[1] = tau;
+    }
+    __syncthreads();
+    const T inv = sh.sc[0], tau = sh.sc[1];
+    // T(0:k, k) = -tau T(0:k, 0:k) (V^T v),  T(k, k) = tau
+    if (tid < k) {
+        T acc = 0;
+        for (int l = tid; l < k; ++l) acc += sh.Ts[tid][l] * sh.gv[l];
+        sh.Ts[tid][k] = -tau * acc;
+    }
+    if (tid == k) sh.Ts[k][k] = tau;
+    // v (stored in place of column k below the diagonal) and the update,
+    // branch free: v_r = 0 above row k, 1 on it, x(r, k) / (alpha - beta) below
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + NT * q;
+        T xk = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == k) xk = x[q][c];
+        const T scaled = xk * inv;
+        const T vr = (r > k) ? scaled : ((r == k) ? (T)1 : (T)0);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c == k) x[q][c] = (r > k) ? scaled : xk;
+            if (c > k && c < w) x[q][c] -= sh.cf[c] * vr;
+        }
+    }
+}
+
+// Steps K, K+1, ..., NB-1 with compile-time column indices.
+template <typename T, int NB, int RPT, int NT, int K>
+struct PanelSteps {
+    static __device__ __forceinline__ void run(int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
+    {
+        if (K >= w) return;
+        panel_step<T, NB, RPT, NT, K>(K, w, x, sh);
+        PanelSteps<T, NB, RPT, NT, K + 1>::run(w, x, sh);
+    }
+};
+template <typename T, int NB, int RPT, int NT>
+struct PanelSteps<T, NB, RPT, NT, NB> {
+    static __device__ __forceinline__ void run(int, T (&)[RPT][NB], PanelShared<T, NB, NT>&) {}
+};
+
+// The column loop is unrolled (static register indices) for the shapes
+// where that keeps the panel free of register spills, and left rolled
+// otherwise (see QR_SHAPES).
+template <typename T, int NB, int RPT, int NT, bool UNROLL>
+__global__ __launch_bounds__(NT) void qr_panel_kernel(int64_t h, int w, T* __restrict__ W, int64_t ldw,
+                                                      T* __restrict__ V, int64_t ldv,
+                                                      T* __restrict__ Tout)
+{
+    __shared__ PanelShared<T, NB, NT> sh;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < NB * NB; e += NT) sh.Ts[e / NB][e % NB] = 0;
     T x[RPT][NB];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const int64_t r = tid + QR_THREADS * q;
+        const int64_t r = tid + NT * q;
 #pragma unroll
         for (int c = 0; c < NB; ++c) x[q][c] = (r < h && c < w) ? W[r + c * ldw] : (T)0;
     }
-    for (int k = 0; k < w; ++k) {
-        // sigma = sum_{r > k} x(r, k)^2
-        T part = 0;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int64_t r = tid + QR_THREADS * q;
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c == k && r > k) part += x[q][c] * x[q][c];
-        }
-        part = wave_sum(part);
-        if (lane == 0) rs[wid] = part;
-        __syncthreads();
-        if (tid == k) {
-            T sigma = 0;
-            for (int i = 0; i < QR_WAVES; ++i) sigma += rs[i];
-            T alpha = 0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c == k) alpha = x[0][c];
-            T beta, tau, scl;
-            if (sigma == (T)0) {
-                beta = alpha; tau = 0; scl = 0;
-            } else {
-                const T nrm = sqrt(alpha * alpha + sigma);
-                beta = (alpha >= (T)0) ? -nrm : nrm;
-                tau = (beta - alpha) / beta;
-                scl = (T)1 / (alpha - beta);
-            }
-            sc[0] = beta; sc[1] = tau; sc[2] = scl;
-        }
-        __syncthreads();
-        const T beta = sc[0], tau = sc[1], scl = sc[2];
-        // v: scaled below the diagonal, 1 on it, 0 above
-        T vr[RPT];
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int64_t r = tid + QR_THREADS * q;
-            T cur = 0;
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c == k) {
-                    if (r > k && tau != (T)0) x[q][c] *= scl;
-                    cur = x[q][c];
-                }
-            vr[q] = (r > k) ? ((tau != (T)0) ? cur : (T)0) : (r == k ? (T)1 : (T)0);
-        }
-        // vals[c < k] = V(:, c)^T v ; vals[c > k] = v^T P(:, c)
-        T vals[NB];
-#pragma unroll
-        for (int c = 0; c < NB; ++c) vals[c] = 0;
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int64_t r = tid + QR_THREADS * q;
-#pragma unroll
-            for (int c = 0; c < NB; ++c) {
-                T vc;
-                if (c < k) vc = (r > c) ? x[q][c] : (r == c ? (T)1 : (T)0);
-                else if (c > k && c < w) vc = x[q][c];
-                else vc = 0;
-                vals[c] += vc * vr[q];
-            }
-        }
-        batched_block_sum<T, NB>(vals, red, bc, QR_WAVES);
-        // rank-1 update of the remaining panel columns
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c > k && c < w) x[q][c] -= tau * bc[c] * vr[q];
-        }
-        // T(0:k, k) = -tau T(0:k, 0:k) (V^T v),  T(k, k) = tau
-        if (tid < k) {
-            T s = 0;
-            for (int l = tid; l < k; ++l) s += Ts[tid][l] * bc[l];
-            Ts[tid][k] = -tau * s;
-        }
-        if (tid == k) {
-            Ts[k][k] = tau;
-#pragma unroll
-            for (int c = 0; c < NB; ++c)
-                if (c == k) x[0][c] = beta;
-        }
+    if constexpr (UNROLL) {
+        PanelSteps<T, NB, RPT, NT, 0>::run(w, x, sh);
+    } else {
+        for (int k = 0; k < w; ++k) panel_step<T, NB, RPT, NT, -1>(k, w, x, sh);
     }
     __syncthreads();
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
-        const int64_t r = tid + QR_THREADS * q;
+        const int64_t r = tid + NT * q;
         if (r >= h) continue;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
@@ -172,35 +200,34 @@ __global__ __launch_bounds__(QR_THREADS) void qr_panel_kernel(int64_t h, int w, 
             V[r + c * ldv] = (r > c) ? val : (r == c ? (T)1 : (T)0);
         }
     }
-    for (int e = tid; e < NB * NB; e += QR_THREADS) Tout[(e % NB) + (e / NB) * NB] = Ts[e % NB][e / NB];
+    for (int e = tid; e < NB * NB; e += NT) Tout[(e % NB) + (e / NB) * NB] = sh.Ts[e % NB][e / NB];
 }
 
 // Z(:, j) = T^T sum_z P[z](j, :)^T for each column j of the trailing matrix.
-// P[z] is (rem x NB, ld rem) = partial (W_trail^T V).
+// P[z] is (rem x w, ld rem) = partial (W_trail^T V).  A work-group handles 16
+// columns: the split partials are summed by (column, entry) threads into LDS,
+// then each (column, entry) thread forms one entry of T^T y.
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void qr_tz_kernel(int64_t rem, int w, const T* __restrict__ P,
                                                     int64_t splits, const T* __restrict__ Tm,
                                                     T* __restrict__ Z)
 {
     __shared__ T Ts[NB * NB];
+    __shared__ T ys[NB][16];
     for (int e = threadIdx.x; e < NB * NB; e += 256) Ts[e] = Tm[e];
-    __syncthreads();
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= rem) return;
-    T y[NB];
-#pragma unroll
-    for (int c = 0; c < NB; ++c) {
+    const int jl = threadIdx.x & 15;
+    const int64_t j = (int64_t)blockIdx.x * 16 + jl;
+    for (int l = threadIdx.x >> 4; l < NB; l += 16) {
         T s = 0;
-        if (c < w)
-            for (int64_t z = 0; z < splits; ++z) s += P[z * rem * w + j + c * rem];
-        y[c] = s;
+        if (j < rem && l < w)
+            for (int64_t z = 0; z < splits; ++z) s += P[z * rem * w + j + (int64_t)l * rem];
+        ys[l][jl] = s;
     }
-#pragma unroll
-    for (int i = 0; i < NB; ++i) {
-        if (i >= w) continue;
+    __syncthreads();
+    for (int i = threadIdx.x >> 4; i < NB; i += 16) {
+        if (j >= rem || i >= w) continue;
         T s = 0;
-#pragma unroll
-        for (int l = 0; l <= i; ++l) s += Ts[l + i * NB] * y[l];
+        for (int l = 0; l <= i; ++l) s += Ts[l + i * NB] * ys[l][jl];
         Z[i + j * NB] = s;
     }
 }
@@ -259,40 +286,27 @@ __global__ __launch_bounds__(1024) void r_diag_check_kernel(int64_t n, const dou
     }
 }
 
-struct QrShape {
-    int nb, rpt;
-};
-// rows per thread from the fixed menu of spill-free instantiations
-static int qr_rpt(int64_t s)
-{
-    const int need = (int)ceil_div(s, QR_THREADS);
-    for (int r : {1, 2, 4, 6, 8, 12})
-        if (r >= need) return r;
-    return 0;
-}
-// panel width: 16 while the panel fits the 256 architectural VGPRs, else 8
+// Panel width per factorization: 16, except FP64 sketches taller than 2048
+// rows, which use 8 (register budget of the panel kernel).
 template <typename T>
-static QrShape qr_shape(int64_t s)
+static int qr_nb(int64_t s)
 {
-    const int rpt = qr_rpt(s);
-    if (!rpt) return {0, 0};
-    const int max16 = sizeof(T) == 8 ? 4 : 8;
-    return {rpt <= max16 ? 16 : 8, rpt};
+    if (s > 6144) return 0;
+    return (sizeof(T) == 8 && s > 2048) ? 8 : 16;
 }
 
 bool qr_supported(int64_t s, int prec)
 {
-    return prec == PNE_PREC_FP64 ? qr_shape<double>(s).nb > 0 : qr_shape<float>(s).nb > 0;
+    return prec == PNE_PREC_FP64 ? qr_nb<double>(s) > 0 : qr_nb<float>(s) > 0;
 }
 
 // upper bound of plan_splitk(h, tiles) over all panels (h <= s)
-static int64_t qr_max_splits(int64_t s) { return (s / 256 > 1 ? s / 256 : 1) + 1; }
+static int64_t qr_max_splits(int64_t s) { return (s / 128 > 1 ? s / 128 : 1) + 1; }
 
 template <typename T>
 static size_t qr_bytes(int64_t s, int64_t n)
 {
-    QrShape sh = qr_shape<T>(s);
-    const int nb = sh.nb ? sh.nb : 8;
+    const int nb = qr_nb<T>(s) ? qr_nb<T>(s) : 8;
     const int64_t splits = qr_max_splits(s);
     Arena ar(nullptr, 0);
     ar.take<T>((size_t)s * nb);          // V
@@ -307,26 +321,32 @@ size_t qr_workspace_bytes(int64_t s, int64_t n, int prec)
     return prec == PNE_PREC_FP64 ? qr_bytes<double>(s, n) : qr_bytes<float>(s, n);
 }
 
-template <typename T, int NB, int RPT>
+template <typename T, int NB, int RPT, int NT, bool U>
 static void panel_launch(int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm, hipStream_t st)
 {
-    qr_panel_kernel<T, NB, RPT><<<1, QR_THREADS, 0, st>>>(h, w, Wp, ldw, V, ldv, Tm);
+    qr_panel_kernel<T, NB, RPT, NT, U><<<1, NT, 0, st>>>(h, w, Wp, ldw, V, ldv, Tm);
 }
 
-// rows per thread: the smallest instantiated value covering the panel height
+// Panel shapes (rows per thread, threads, unrolled column loop): the
+// smallest instantiation covering the panel height; unrolled only where the
+// compiled kernel is free of register spills.
 template <typename T, int NB>
-static void panel_dispatch(int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm,
-                           hipStream_t st)
+static void panel_dispatch(int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm, hipStream_t st)
 {
-    constexpr int MAXR = (NB == 16) ? (sizeof(T) == 8 ? 4 : 8) : 12;
-    const int r = qr_rpt(h);
-    if (r <= 1) panel_launch<T, NB, 1>(h, w, Wp, ldw, V, ldv, Tm, st);
-    else if (r <= 2) panel_launch<T, NB, 2>(h, w, Wp, ldw, V, ldv, Tm, st);
-    else if (r <= 4) panel_launch<T, NB, 4>(h, w, Wp, ldw, V, ldv, Tm, st);
-    else if constexpr (MAXR >= 8) {
-        if (r <= 6) panel_launch<T, NB, 6>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (r <= 8) panel_launch<T, NB, 8>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if constexpr (MAXR >= 12) panel_launch<T, NB, 12>(h, w, Wp, ldw, V, ldv, Tm, st);
+    if constexpr (sizeof(T) == 4) {
+        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else if (h <= 2048) panel_launch<T, NB, 2, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else panel_launch<T, NB, 12, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+    } else if constexpr (NB == 16) {
+        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else panel_launch<T, NB, 4, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+    } else {
+        if (h <= 2048) panel_launch<T, NB, 4, 512, true>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        else panel_launch<T, NB, 12, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
     }
 }
 
@@ -335,9 +355,8 @@ static int qr_run(int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, 
                   int32_t* info, void* work, size_t work_bytes, hipStream_t st)
 {
     if (work_bytes < qr_bytes<T>(s, n)) return PNE_EWORKSPACE;
-    QrShape sh = qr_shape<T>(s);
-    if (!sh.nb) return PNE_ENOTSUP;
-    const int NBv = sh.nb;
+    const int NBv = qr_nb<T>(s);
+    if (!NBv) return PNE_ENOTSUP;
     const int64_t splits_max = qr_max_splits(s);
     Arena ar(work, work_bytes);
     T* V = ar.take<T>((size_t)s * NBv);
@@ -368,8 +387,8 @@ static int qr_run(int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, 
         g.P = P;
         if constexpr (sizeof(T) == 8) gemm_f64_partials(g, st);
         else gemm_f32_partials(g, st);
-        if (NBv == 16) qr_tz_kernel<T, 16><<<ceil_div(rem, 256), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
-        else qr_tz_kernel<T, 8><<<ceil_div(rem, 256), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
+        if (NBv == 16) qr_tz_kernel<T, 16><<<ceil_div(rem, 16), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
+        else qr_tz_kernel<T, 8><<<ceil_div(rem, 16), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
         // W_trail -= V Z
         GemmArgs u{};
         u.M = h; u.N = rem; u.K = w;

@@ -1,6 +1,6 @@
 // A_p = A R_s^{-1} in FP64 (Algorithm 1, "Solve A_p = A R_s^{-1}", after
 // R_s is promoted to double).  Blocked right-side substitution over column
-// blocks of 64:
+// blocks J:
 //   A_p(:, J) = A(:, J) - A_p(:, <J) R(<J, J)     (MFMA GEMM, gemm.hip)
 //   A_p(:, J) := A_p(:, J) R(J, J)^{-1}           (row-parallel substitution)
 // The second step keeps one row per lane in registers and runs the plain
@@ -33,13 +33,14 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(int64_t m, int w, T* __r
     T x[LEAF];
 #pragma unroll
     for (int c = 0; c < LEAF; ++c) x[c] = (c < w) ? X[i * rs + c * cs] : (T)0;
+    // column-oriented substitution: once y_c is final it is removed from every
+    // later entry; y_j still accumulates its terms in the order k = 0, 1, ...
 #pragma unroll
     for (int c = 0; c < LEAF; ++c) {
         if (c < w) {
-            T acc = x[c];
+            if (!UNIT) x[c] = x[c] / Rs[c * LEAF + c];
 #pragma unroll
-            for (int k = 0; k < c; ++k) acc -= x[k] * Rs[c * LEAF + k];
-            x[c] = UNIT ? acc : acc / Rs[c * LEAF + c];
+            for (int j = c + 1; j < LEAF; ++j) x[j] -= x[c] * Rs[j * LEAF + c];
         }
     }
 #pragma unroll
@@ -58,11 +59,14 @@ template void trsm_leaf<float, true, false>(int64_t, int, float*, int64_t, int64
 template void trsm_leaf<double, true, true>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
 template void trsm_leaf<double, false, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
 
+// Column blocks of 128: one GEMM brings the block up to date with every
+// earlier column, then the two 64-column halves are finished by the leaf with
+// a 64-deep GEMM in between.
 void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
                       int64_t ldr, double* Ap, int64_t ldap, hipStream_t st)
 {
-    for (int64_t c0 = 0; c0 < n; c0 += LEAF) {
-        const int w = (int)((n - c0 < LEAF) ? n - c0 : LEAF);
+    for (int64_t c0 = 0; c0 < n; c0 += 2 * LEAF) {
+        const int w = (int)((n - c0 < 2 * LEAF) ? n - c0 : 2 * LEAF);
         GemmArgs g{};
         g.M = m; g.N = w; g.K = c0;
         g.A = Ap; g.lda = ldap; g.transA = 0;
@@ -72,7 +76,21 @@ void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const 
         g.C = Ap + c0 * ldap; g.ldc = ldap;
         g.splits = 1;
         gemm_f64(g, st);
-        trsm_leaf<double, false, false>(m, w, Ap + c0 * ldap, 1, ldap, R + c0 + c0 * ldr, ldr, st);
+        const int w1 = w < LEAF ? w : LEAF;
+        trsm_leaf<double, false, false>(m, w1, Ap + c0 * ldap, 1, ldap, R + c0 + c0 * ldr, ldr, st);
+        if (w > LEAF) {
+            const int64_t c1 = c0 + LEAF;
+            GemmArgs h{};
+            h.M = m; h.N = w - LEAF; h.K = LEAF;
+            h.A = Ap + c0 * ldap; h.lda = ldap; h.transA = 0;
+            h.B = R + c0 + c1 * ldr; h.ldb = ldr; h.transB = 0;
+            h.alpha = -1.0; h.beta = 1.0;
+            h.Cin = Ap + c1 * ldap; h.ldcin = ldap;
+            h.C = Ap + c1 * ldap; h.ldc = ldap;
+            h.splits = 1;
+            gemm_f64(h, st);
+            trsm_leaf<double, false, false>(m, w - LEAF, Ap + c1 * ldap, 1, ldap, R + c1 + c1 * ldr, ldr, st);
+        }
     }
 }
 

@@ -1,7 +1,5 @@
 // n-vector kernels of the solve and refinement steps (FP64 unless stated):
-// single-work-group triangular solves (blocked: a 64-row diagonal block is
-// solved by one wavefront with shuffles, the rows below/above are updated by
-// all threads), the residual r = b - A x, the product y = X^T v split over
+// single-work-group triangular solves (trsv_dev.h), the residual r = b - A x, the product y = X^T v split over
 // rows with a fixed-order reduction, and small helpers.
 #include "common.h"
 #include "kernels.h"
@@ -16,10 +14,11 @@ __global__ __launch_bounds__(TV_THREADS) void trsv_kernel(int64_t n, const T* __
                                                           int uplo, int trans, int unit, T* __restrict__ x)
 {
     extern __shared__ unsigned char smem[];
+    __shared__ T dblk[TB * TBL];
     T* xs = (T*)smem;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = x[i];
     __syncthreads();
-    wg_trsv<T>(n, M, ld, (uplo == 0) != (trans != 0), trans != 0, unit != 0, xs);
+    wg_trsv<T>(n, M, ld, (uplo == 0) != (trans != 0), trans != 0, unit != 0, xs, dblk);
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
 }
 
@@ -31,35 +30,53 @@ void trsv(int64_t n, const T* M, int64_t ld, int uplo, int trans, int unit, T* x
 template void trsv<double>(int64_t, const double*, int64_t, int, int, int, double*, hipStream_t);
 template void trsv<float>(int64_t, const float*, int64_t, int, int, int, float*, hipStream_t);
 
-// PNE solve in one launch: L z = c, L^T y = z, R x = y.
+size_t dinv_elems(int64_t n) { return (size_t)((n + TB - 1) / TB) * TB * TB; }
+
+template <typename T>
+void inv_diag_blocks(int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv, hipStream_t st)
+{
+    inv_diag_blocks_kernel<T><<<(n + TB - 1) / TB, 64, 0, st>>>(n, M, ld, lower, trans, unit, Dinv);
+}
+template void inv_diag_blocks<double>(int64_t, const double*, int64_t, int, int, int, double*, hipStream_t);
+template void inv_diag_blocks<float>(int64_t, const float*, int64_t, int, int, int, float*, hipStream_t);
+
+// PNE solve in one launch: L z = c, L^T y = z, R x = y, with the inverted
+// diagonal blocks DL of L and DR of R.
 __global__ __launch_bounds__(TV_THREADS) void pne_solve3_kernel(int64_t n, const double* __restrict__ L,
-                                                                int64_t ldl, const double* __restrict__ R,
-                                                                int64_t ldr, const double* __restrict__ c,
+                                                                int64_t ldl, const double* __restrict__ DL,
+                                                                const double* __restrict__ R, int64_t ldr,
+                                                                const double* __restrict__ DR,
+                                                                const double* __restrict__ c,
                                                                 double* __restrict__ x)
 {
     extern __shared__ unsigned char smem[];
+    __shared__ double tmp[TB];
     double* xs = (double*)smem;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = c[i];
     __syncthreads();
-    wg_trsv<double>(n, L, ldl, true, false, false, xs);
-    wg_trsv<double>(n, L, ldl, false, true, false, xs);
-    wg_trsv<double>(n, R, ldr, false, false, false, xs);
+    wg_trsv_inv<double>(n, L, ldl, true, false, DL, false, xs, tmp);
+    wg_trsv_inv<double>(n, L, ldl, false, true, DL, true, xs, tmp);
+    wg_trsv_inv<double>(n, R, ldr, false, false, DR, false, xs, tmp);
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
 }
 
-void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* R, int64_t ldr, const double* c,
-                double* x, hipStream_t st)
+void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* DL, const double* R, int64_t ldr,
+                const double* DR, const double* c, double* x, hipStream_t st)
 {
-    pne_solve3_kernel<<<1, TV_THREADS, n * sizeof(double), st>>>(n, L, ldl, R, ldr, c, x);
+    pne_solve3_kernel<<<1, TV_THREADS, n * sizeof(double), st>>>(n, L, ldl, DL, R, ldr, DR, c, x);
 }
 
-// HPNE solve: x = U^{-1} L^{-1} P c (row exchanges in order, unit lower L).
+// HPNE solve: x = U^{-1} L^{-1} P c (row exchanges in order, unit lower L),
+// with the inverted diagonal blocks DL (unit lower) and DU (upper).
 __global__ __launch_bounds__(TV_THREADS) void lu_solve_kernel(int64_t n, const double* __restrict__ LU,
                                                               int64_t ld, const int32_t* __restrict__ piv,
+                                                              const double* __restrict__ DL,
+                                                              const double* __restrict__ DU,
                                                               const double* __restrict__ c,
                                                               double* __restrict__ x)
 {
     extern __shared__ unsigned char smem[];
+    __shared__ double tmp[TB];
     double* xs = (double*)smem;
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) xs[i] = c[i];
     __syncthreads();
@@ -69,20 +86,15 @@ __global__ __launch_bounds__(TV_THREADS) void lu_solve_kernel(int64_t n, const d
             if (p != k) { double t = xs[k]; xs[k] = xs[p]; xs[p] = t; }
         }
     __syncthreads();
-    wg_trsv<double>(n, LU, ld, true, false, true, xs);
-    wg_trsv<double>(n, LU, ld, false, false, false, xs);
+    wg_trsv_inv<double>(n, LU, ld, true, false, DL, false, xs, tmp);
+    wg_trsv_inv<double>(n, LU, ld, false, false, DU, false, xs, tmp);
     for (int64_t i = threadIdx.x; i < n; i += blockDim.x) x[i] = xs[i];
 }
 
-void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* c, double* x,
-               hipStream_t st)
+void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL, const double* DU,
+               const double* c, double* x, hipStream_t st)
 {
-    lu_solve_kernel<<<1, TV_THREADS, n * sizeof(double), st>>>(n, LU, ld, piv, c, x);
-}
-
-void lu_solve(int64_t n, const double* LU, int64_t ld, const int32_t* piv, double* x, hipStream_t st)
-{
-    lu_solve_kernel<<<1, TV_THREADS, n * sizeof(double), st>>>(n, LU, ld, piv, x, x);
+    lu_solve_kernel<<<1, TV_THREADS, n * sizeof(double), st>>>(n, LU, ld, piv, DL, DU, c, x);
 }
 
 // r = b - A x, one row per thread, x staged in LDS in chunks of 4096.
