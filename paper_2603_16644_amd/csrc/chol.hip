@@ -14,9 +14,43 @@ namespace pne {
 constexpr int CB = 64;
 
 // Unblocked Cholesky of one w x w (w <= 64) diagonal block: lane i of every
-// wave holds row i; wave q holds columns 16q .. 16q+15 in registers.  Step k:
-// the owner wave of column k forms L(:, k) and publishes it in LDS; every wave
+// wave holds row i; wave q holds columns 16q .. 16q+15 in registers.  Step k
+// (unrolled, so every register index is static): the owner wave of column k
+// forms L(:, k) = C(:, k) / sqrt(C(k, k)) and publishes it in LDS; every wave
 // then updates its columns j > k: L(i, j) -= L(i, k) L(j, k).
+template <typename T, int K>
+struct CholSteps {
+    static __device__ __forceinline__ void run(int w, T (&a)[16], T* lcol, int32_t* info, int64_t c0)
+    {
+        if (K >= w) return;
+        const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+        constexpr int QK = K >> 4, TK = K & 15;
+        if (q == QK) {
+            const T d = __shfl(a[TK], K, 64);
+            const bool bad = !(d > (T)0) || !isfinite(d);
+            if (bad && lane == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + K) + 1;
+            const T lkk = bad ? (T)NAN : (T)sqrt(d);
+            const T rl = (T)1 / lkk;
+            const T l = (lane > K) ? a[TK] * rl : (lane == K ? lkk : (T)0);
+            a[TK] = l;
+            lcol[lane] = l;
+        }
+        __syncthreads();
+        const T li = lcol[lane];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int j = 16 * q + t;
+            if (j > K) a[t] -= li * lcol[j];
+        }
+        __syncthreads();
+        CholSteps<T, K + 1>::run(w, a, lcol, info, c0);
+    }
+};
+template <typename T>
+struct CholSteps<T, CB> {
+    static __device__ __forceinline__ void run(int, T (&)[16], T*, int32_t*, int64_t) {}
+};
+
 template <typename T>
 __global__ __launch_bounds__(256) void potrf_diag_kernel(int w, T* __restrict__ C, int64_t ldc,
                                                          int32_t* __restrict__ info, int64_t c0)
@@ -29,32 +63,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(int w, T* __restrict__ 
         const int j = 16 * q + t;
         a[t] = (lane < w && j < w && lane >= j) ? C[lane + (int64_t)j * ldc] : (T)0;
     }
-    for (int k = 0; k < w; ++k) {
-        const int qk = k >> 4, tk = k & 15;
-        if (q == qk) {
-            T v = 0;
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (t == tk) v = a[t];
-            const T d = __shfl(v, k, 64);
-            const bool bad = !(d > (T)0) || !isfinite(d);
-            if (bad && lane == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + k) + 1;
-            const T lkk = bad ? (T)NAN : (T)sqrt(d);
-            const T l = (lane > k) ? v / lkk : (lane == k ? lkk : (T)0);
-#pragma unroll
-            for (int t = 0; t < 16; ++t)
-                if (t == tk) a[t] = l;
-            lcol[lane] = l;
-        }
-        __syncthreads();
-        const T li = lcol[lane];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) {
-            const int j = 16 * q + t;
-            if (j > k) a[t] -= li * lcol[j];
-        }
-        __syncthreads();
-    }
+    CholSteps<T, 0>::run(w, a, lcol, info, c0);
 #pragma unroll
     for (int t = 0; t < 16; ++t) {
         const int j = 16 * q + t;

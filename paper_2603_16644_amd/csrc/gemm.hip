@@ -291,14 +291,27 @@ int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn)
     return tm * tn;
 }
 
+// Split-K plan for a product with `tiles` output tiles: the number of splits
+// (chunks of at least 128 along K) whose work-group count fills whole waves of
+// the machine best (256 CUs x 2 resident work-groups), preferring more
+// work-groups when the fill is equal.
 void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk)
 {
-    int64_t want = ceil_div(1024, tiles < 1 ? 1 : tiles);
+    const int64_t slots = 512;
+    if (tiles < 1) tiles = 1;
     int64_t maxs = K / 128;
     if (maxs < 1) maxs = 1;
-    int64_t s = want < maxs ? want : maxs;
-    if (s < 1) s = 1;
-    int64_t kc = ceil_div(ceil_div(K, s), G_BK) * G_BK;
+    if (maxs > 4 * slots) maxs = 4 * slots;
+    int64_t best = 1;
+    double best_eff = -1.0;
+    for (int64_t sp = 1; sp <= maxs; ++sp) {
+        const int64_t wg = tiles * sp;
+        const int64_t waves = (wg + slots - 1) / slots;
+        if (waves > 4) break;
+        double eff = (double)wg / (double)(waves * slots);
+        if (eff > best_eff + 1e-9) { best_eff = eff; best = sp; }
+    }
+    const int64_t kc = ceil_div(ceil_div(K, best), G_BK) * G_BK;
     *kchunk = kc;
     *splits = ceil_div(K, kc);
 }

@@ -14,13 +14,13 @@ namespace pne {
 
 constexpr int LEAF = 64;
 
-template <typename T, bool TRANS_LOWER, bool UNIT>
-__global__ __launch_bounds__(256) void trsm_leaf_kernel(int64_t m, int w, T* __restrict__ X,
+template <typename T, bool TRANS_LOWER, bool UNIT, int NTH>
+__global__ __launch_bounds__(NTH) void trsm_leaf_kernel(int64_t m, int w, T* __restrict__ X,
                                                         int64_t rs, int64_t cs,
                                                         const T* __restrict__ Rb, int64_t ldr)
 {
     __shared__ T Rs[LEAF * LEAF];  // Rs[c * 64 + k] = R(k, c), k <= c
-    for (int e = threadIdx.x; e < LEAF * LEAF; e += 256) {
+    for (int e = threadIdx.x; e < LEAF * LEAF; e += NTH) {
         const int c = e / LEAF, k = e % LEAF;
         T v = 0;
         if (c < w && k <= c) v = TRANS_LOWER ? Rb[c + (int64_t)k * ldr] : Rb[k + (int64_t)c * ldr];
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(256) void trsm_leaf_kernel(int64_t m, int w, T* __r
         Rs[e] = v;
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t i = (int64_t)blockIdx.x * NTH + threadIdx.x;
     if (i >= m) return;
     T x[LEAF];
 #pragma unroll
@@ -52,7 +52,10 @@ template <typename T, bool TL, bool UNIT>
 void trsm_leaf(int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr, hipStream_t st)
 {
     if (m <= 0) return;
-    trsm_leaf_kernel<T, TL, UNIT><<<ceil_div(m, 256), 256, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
+    // short panels (factorizations) use one wavefront per work-group to
+    // spread over more compute units
+    if (m < 16384) trsm_leaf_kernel<T, TL, UNIT, 64><<<ceil_div(m, 64), 64, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
+    else trsm_leaf_kernel<T, TL, UNIT, 256><<<ceil_div(m, 256), 256, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
 }
 template void trsm_leaf<double, true, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
 template void trsm_leaf<float, true, false>(int64_t, int, float*, int64_t, int64_t, const float*, int64_t, hipStream_t);
