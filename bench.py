@@ -34,6 +34,7 @@ PEAK_FP64 = 78.6e12      # dense FP64 MFMA, FLOP/s
 PEAK_BF16 = 2.5e15       # dense BF16 MFMA, FLOP/s
 PEAK_HBM = 8.0e12        # B/s
 U64 = 2.0 ** -53
+COPY_PROBE_BYTES = 512 << 20   # read once and written once by the copy probe
 
 
 def parse():
@@ -43,6 +44,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="mixed path only (profiling runs)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run one plain elementwise copy (torch.neg) of 512 MiB first, so that "
+                         "hardware byte counters can be scaled against a kernel of known traffic")
     return ap.parse_args()
 
 
@@ -179,6 +183,12 @@ def main():
     print(f"[bench] generating m={M} n={N} kappa={KAPPA:g} rho={RHO:g}", file=sys.stderr, flush=True)
     prob = make_problem(M, N, KAPPA, RHO, seed=1002, device="cuda")
     torch.cuda.synchronize()
+    if args.copy_probe:
+        src = torch.zeros(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     bound = KAPPA * U64 * (1 + KAPPA * RHO)
 
     mixed = pne.make_opts(s=S, seed=2, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)

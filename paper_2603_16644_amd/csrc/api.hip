@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <vector>
+
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
@@ -18,6 +20,7 @@ struct Problem {
     int hpne;
     int refine;
     int64_t br;
+    int64_t kchunk_fixed;   // 0: one problem on the machine; > 0: batch planning
 };
 
 bool valid_prec(int p, bool allow_auto, bool allow_fp8)
@@ -59,17 +62,19 @@ struct Buffers {
 
 size_t scratch_bytes(const Problem& p, int sk, int qr)
 {
-    size_t b = sketch_workspace_bytes(p.m, p.n, p.s, sk, p.br);
+    size_t b = sketch_workspace_bytes(p.m, p.n, p.s, sk, p.br, p.kchunk_fixed);
     size_t q = qr_workspace_bytes(p.s, p.n, qr);
     if (q > b) b = q;
     int64_t splits, kc;
-    plan_splitk(p.m, gemm_tiles(p.n, p.n, !p.hpne, 128), &splits, &kc);
+    plan_splitk(p.m, gemm_tiles(p.n, p.n, !p.hpne, 128), &splits, &kc, p.kchunk_fixed);
     size_t g = ((size_t)splits * p.n * p.n + (size_t)splits * p.n) * sizeof(double) + 512;
     if (g > b) b = g;
     return b;
 }
 
-size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_condest)
+// Workspace of one problem; `own_k0` = false leaves k0/choice out (the batch
+// keeps them in arrays of its own).
+size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_condest, bool own_k0 = true)
 {
     int sk[3], qr[3], nsk, nqr;
     candidates(p.sketch_prec, sk, &nsk);
@@ -83,7 +88,7 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
             if (qr[j] == PNE_PREC_FP64) any64 = true;
         }
     if (with_condest) {
-        size_t ce = condest_workspace_bytes(p.m, p.n);
+        size_t ce = condest_workspace_bytes(p.m, p.n, p.kchunk_fixed);
         if (ce > scr) scr = ce;
     }
     Arena ar(base, cap);
@@ -101,8 +106,10 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
     b.gv = ar.take<double>(gemv_t_partials(p.m, p.n));
     b.dinv1 = ar.take<double>(dinv_elems(p.n));
     b.dinv2 = ar.take<double>(dinv_elems(p.n));
-    b.k0 = ar.take<float>(4);
-    b.choice = ar.take<int32_t>(4);
+    if (own_k0) {
+        b.k0 = ar.take<float>(4);
+        b.choice = ar.take<int32_t>(4);
+    }
     if (out) *out = b;
     return ar.used;
 }
@@ -127,7 +134,7 @@ pne_status check_common(int64_t m, int64_t n, const void* dA, int64_t lda, const
     return PNE_OK;
 }
 
-Problem make_problem(int64_t m, int64_t n, int64_t lda, const pne_opts* o, int hpne)
+Problem make_problem(int64_t m, int64_t n, int64_t lda, const pne_opts* o, int hpne, int64_t kchunk_fixed = 0)
 {
     Problem p;
     p.m = m; p.n = n; p.lda = lda;
@@ -137,24 +144,30 @@ Problem make_problem(int64_t m, int64_t n, int64_t lda, const pne_opts* o, int h
     p.hpne = hpne;
     p.refine = o->refine_steps;
     p.br = o->block_rows > 0 ? o->block_rows : 128;
+    p.kchunk_fixed = kchunk_fixed;
     return p;
 }
 
+inline void mark(Exec& ex, int phase)
+{
+    if (!ex.recording()) prof_mark(phase, ex.st);
+}
+
 // Resolve AUTO through the condition estimate (one host synchronisation).
-pne_status resolve_precision(const Problem& p, const double* dA, const pne_opts* o, const Buffers& b,
-                             size_t scratch_cap, hipStream_t st, int* sk, int* qr, float* k0)
+pne_status resolve_precision(Exec& ex, const Problem& p, const double* dA, const pne_opts* o, const Buffers& b,
+                             size_t scratch_cap, int* sk, int* qr, float* k0)
 {
     *sk = p.sketch_prec;
     *qr = p.qr_prec;
     *k0 = NAN;
     if (*sk != PNE_PREC_AUTO && *qr != PNE_PREC_AUTO) return PNE_OK;
-    int rc = condest_run(p.m, p.n, dA, p.lda, o->known_kappa, b.k0, b.choice, b.scratch, scratch_cap, st);
+    int rc = condest_run(ex, p.m, p.n, dA, p.lda, o->known_kappa, b.k0, b.choice, b.scratch, scratch_cap);
     if (rc) return (pne_status)rc;
     float hk0;
     int32_t hch;
-    HIP_OK(hipMemcpyAsync(&hk0, b.k0, sizeof(float), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipMemcpyAsync(&hch, b.choice, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-    HIP_OK(hipStreamSynchronize(st));
+    HIP_OK(hipMemcpyAsync(&hk0, b.k0, sizeof(float), hipMemcpyDeviceToHost, ex.st));
+    HIP_OK(hipMemcpyAsync(&hch, b.choice, sizeof(int32_t), hipMemcpyDeviceToHost, ex.st));
+    HIP_OK(hipStreamSynchronize(ex.st));
     if (*sk == PNE_PREC_AUTO) *sk = hch;
     if (*qr == PNE_PREC_AUTO) *qr = hch;
     *k0 = hk0;
@@ -163,18 +176,81 @@ pne_status resolve_precision(const Problem& p, const double* dA, const pne_opts*
 
 size_t scratch_cap_of(const Buffers& b) { return (size_t)((char*)b.W - (char*)b.scratch); }
 
-// sketch + QR -> b.R; returns status
-pne_status run_precond(const Problem& p, const double* dA, const pne_opts* o, int sk, int qr,
-                       const Buffers& b, int32_t* dinfo, hipStream_t st)
+// sketch + QR -> b.R
+pne_status run_precond(Exec& ex, const Problem& p, const double* dA, uint64_t seed, uint32_t pid, int sk,
+                       int qr, const Buffers& b, int32_t* dinfo)
 {
     const bool w64 = (qr == PNE_PREC_FP64);
     const size_t cap = scratch_cap_of(b);
-    int rc = sketch_run(p.m, p.n, dA, p.lda, p.s, o->seed, o->problem_id, sk, p.br,
+    int rc = sketch_run(ex, p.m, p.n, dA, p.lda, p.s, seed, pid, sk, p.br,
                         w64 ? nullptr : (float*)b.W, p.s, w64 ? (double*)b.W : nullptr, p.s,
-                        b.scratch, cap, st);
+                        b.scratch, cap);
     if (rc) return (pne_status)rc;
-    rc = qr_r(p.s, p.n, b.W, p.s, qr, b.R, p.n, dinfo, b.scratch, cap, st);
+    rc = qr_r(ex, p.s, p.n, b.W, p.s, qr, b.R, p.n, dinfo, b.scratch, cap);
+    mark(ex, PH_QR);
     return (pne_status)rc;
+}
+
+// A_p, Gram, factorization, solves and refinement (Algorithm 1 after the
+// preconditioner) for one problem.
+pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double* db, double* dx,
+                     const Buffers& b, int32_t* dinfo)
+{
+    const int64_t m = p.m, n = p.n, lda = p.lda;
+    const int hpne = p.hpne;
+    // A_p = A R_s^{-1}
+    ex.stage(ST_TRSM);
+    trsm_right_upper(ex, m, n, dA, lda, b.R, n, b.Ap, m);
+    mark(ex, PH_TRSM);
+    // C = A_p^T A_p (PNE, lower tiles) or A_p^T A (HPNE); c = A_p^T b
+    ex.stage(ST_GRAM);
+    int64_t splits, kc;
+    plan_splitk(m, gemm_tiles(n, n, !hpne, 128), &splits, &kc, ex.kchunk_fixed);
+    GemmArgs g{};
+    g.M = n; g.N = n; g.K = m;
+    g.A = b.Ap; g.lda = m; g.transA = 1;
+    g.B = hpne ? (const void*)dA : (const void*)b.Ap; g.ldb = hpne ? lda : m; g.transB = 0;
+    g.alpha = 1.0; g.beta = 0.0;
+    g.C = b.C; g.ldc = n;
+    g.lower = !hpne;
+    g.splits = splits; g.kchunk = kc;
+    g.P = b.scratch;
+    g.Pc = (double*)b.scratch + (size_t)splits * n * n;
+    g.bvec = db; g.cvec = b.c;
+    gemm_f64_partials(ex, g);
+    mark(ex, PH_GRAM_GEMM);
+    ex.stage(ST_GRAM_REDUCE);
+    gemm_f64_reduce(ex, g);
+    mark(ex, PH_GRAM_REDUCE);
+    ex.stage(ST_FACTOR);
+    if (hpne) lu_factor(ex, n, b.C, n, b.piv, dinfo);
+    else cholesky<double>(ex, n, b.C, n, dinfo);
+    ex.stage(ST_FACTOR_INV);
+    if (hpne) {
+        inv_diag_blocks<double>(ex, n, b.C, n, 1, 0, 1, b.dinv1);
+        inv_diag_blocks<double>(ex, n, b.C, n, 0, 0, 0, b.dinv2);
+    } else {
+        inv_diag_blocks<double>(ex, n, b.C, n, 1, 0, 0, b.dinv1);
+        inv_diag_blocks<double>(ex, n, b.R, n, 0, 0, 0, b.dinv2);
+    }
+    mark(ex, PH_FACTOR);
+    ex.stage(ST_SOLVE);
+    if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx);
+    else pne_solve3(ex, n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.c, dx);
+    mark(ex, PH_SOLVE);
+    ex.stage(ST_REFINE);
+    for (int k = 0; k < p.refine; ++k) {
+        ex.iter((uint32_t)k);
+        residual(ex, m, n, dA, lda, db, dx, b.r);
+        gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
+        if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d);
+        else pne_solve3(ex, n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.y, b.d);
+        axpy_update(ex, n, dx, b.d);
+    }
+    ex.stage(ST_FINISH);
+    fill_nan_on_info(ex, n, dx, dinfo);
+    mark(ex, PH_REFINE);
+    return PNE_OK;
 }
 
 pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
@@ -189,60 +265,21 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
     Buffers b;
     const size_t need = layout(p, dwork, work_bytes, &b, true);
     if (work_bytes < need) return PNE_EWORKSPACE;
+    Exec ex;
+    ex.st = st;
     prof_reset();
     prof_mark(PH_START, st);
-    zero_i32(1, dinfo, st);
+    ex.stage(ST_INIT);
+    zero_i32(ex, 1, dinfo);
     int sk, qr;
     float k0;
-    pne_status rc = resolve_precision(p, dA, o, b, scratch_cap_of(b), st, &sk, &qr, &k0);
+    pne_status rc = resolve_precision(ex, p, dA, o, b, scratch_cap_of(b), &sk, &qr, &k0);
     if (rc) return rc;
-    prof_mark(PH_CONDEST, st);
-    rc = run_precond(p, dA, o, sk, qr, b, dinfo, st);
+    mark(ex, PH_CONDEST);
+    rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
     if (rc) return rc;
-    prof_mark(PH_QR, st);
-    // A_p = A R_s^{-1}
-    trsm_right_upper(m, n, dA, lda, b.R, n, b.Ap, m, st);
-    prof_mark(PH_TRSM, st);
-    // C = A_p^T A_p (PNE, lower tiles) or A_p^T A (HPNE); c = A_p^T b
-    int64_t splits, kc;
-    plan_splitk(m, gemm_tiles(n, n, !hpne, 128), &splits, &kc);
-    GemmArgs g{};
-    g.M = n; g.N = n; g.K = m;
-    g.A = b.Ap; g.lda = m; g.transA = 1;
-    g.B = hpne ? (const void*)dA : (const void*)b.Ap; g.ldb = hpne ? lda : m; g.transB = 0;
-    g.alpha = 1.0; g.beta = 0.0;
-    g.C = b.C; g.ldc = n;
-    g.lower = !hpne;
-    g.splits = splits; g.kchunk = kc;
-    g.P = b.scratch;
-    g.Pc = (double*)b.scratch + (size_t)splits * n * n;
-    g.bvec = db; g.cvec = b.c;
-    gemm_f64_partials(g, st);
-    prof_mark(PH_GRAM_GEMM, st);
-    gemm_f64_reduce(g, st);
-    prof_mark(PH_GRAM_REDUCE, st);
-    if (hpne) {
-        lu_factor(n, b.C, n, b.piv, dinfo, st);
-        inv_diag_blocks<double>(n, b.C, n, 1, 0, 1, b.dinv1, st);
-        inv_diag_blocks<double>(n, b.C, n, 0, 0, 0, b.dinv2, st);
-    } else {
-        cholesky<double>(n, b.C, n, dinfo, st);
-        inv_diag_blocks<double>(n, b.C, n, 1, 0, 0, b.dinv1, st);
-        inv_diag_blocks<double>(n, b.R, n, 0, 0, 0, b.dinv2, st);
-    }
-    prof_mark(PH_FACTOR, st);
-    if (hpne) lu_solve2(n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, st);
-    else pne_solve3(n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.c, dx, st);
-    prof_mark(PH_SOLVE, st);
-    for (int k = 0; k < p.refine; ++k) {
-        residual(m, n, dA, lda, db, dx, b.r, st);
-        gemv_t(m, n, b.Ap, m, b.r, b.y, b.gv, st);
-        if (hpne) lu_solve2(n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, st);
-        else pne_solve3(n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.y, b.d, st);
-        axpy_update(n, dx, b.d, st);
-    }
-    fill_nan_on_info(n, dx, dinfo, st);
-    prof_mark(PH_REFINE, st);
+    rc = run_solve(ex, p, dA, db, dx, b, dinfo);
+    if (rc) return rc;
     if (hipGetLastError() != hipSuccess) return PNE_EHIP;
     if (hinfo) {
         hinfo->sketch_prec_used = sk;
@@ -251,6 +288,178 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
         hinfo->refine_steps_run = p.refine;
     }
     return PNE_OK;
+}
+
+// ---------------------------------------------------------------- batches
+// Row chunk of the split-K products in a batch: every member's long products
+// are cut into pieces of this many rows, so that work-groups carry similar
+// work across members of very different sizes.
+constexpr int64_t BATCH_KCHUNK = 8192;
+
+struct BatchLayout {
+    float* k0;              // [batch] condition estimates
+    int32_t* choice;        // [batch] precision picks
+    std::vector<Buffers> buf;
+    std::vector<Problem> prob;
+    char* tables;           // group tables
+    size_t table_cap;
+    size_t fixed_bytes;     // everything but the tables
+};
+
+bool batch_auto(const pne_opts* o) { return o->sketch_prec == PNE_PREC_AUTO || o->qr_prec == PNE_PREC_AUTO; }
+
+void batch_layout(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, int hpne, void* base, size_t cap,
+                  BatchLayout* L)
+{
+    Arena ar(base, cap);
+    L->k0 = ar.take<float>(batch);
+    L->choice = ar.take<int32_t>(batch);
+    L->buf.resize(batch);
+    L->prob.resize(batch);
+    const bool with_ce = batch_auto(o);
+    for (int64_t i = 0; i < batch; ++i) {
+        L->prob[i] = make_problem(hd[i].m, hd[i].n, hd[i].lda, o, hpne, BATCH_KCHUNK);
+        const size_t need = layout(L->prob[i], nullptr, 0, nullptr, with_ce, false);
+        char* region = ar.take<char>(need);
+        layout(L->prob[i], region, need, &L->buf[i], with_ce, false);
+        L->buf[i].k0 = L->k0 ? L->k0 + i : nullptr;
+        L->buf[i].choice = L->choice ? L->choice + i : nullptr;
+    }
+    L->fixed_bytes = ar.used;
+    L->tables = base ? (char*)base + ar.used : nullptr;
+    L->table_cap = cap > ar.used ? cap - ar.used : 0;
+}
+
+// Upper bound of the group-table bytes of a recording: every record adds its
+// arguments and two int32 entries, and at most one group header, one
+// alignment pad and one 256-byte table alignment.
+size_t table_bound(const Recorder& rec)
+{
+    size_t b = 256;
+    for (const LaunchRec& r : rec.recs) b += r.args_size + 8 + 4 + 16 + 256;
+    return b;
+}
+
+// Records the launches of every member (main pipeline with the resolved
+// precisions sk/qr per member).
+pne_status record_batch(Recorder& rec, int64_t batch, const pne_problem_desc* hd, const double* dA_base,
+                        const double* db_base, double* dx_base, const pne_opts* o, const BatchLayout& L,
+                        const int32_t* sk, const int32_t* qr, int32_t* dinfo)
+{
+    for (int64_t i = 0; i < batch; ++i) {
+        Exec ex;
+        ex.rec = &rec;
+        ex.member = (int32_t)i;
+        ex.kchunk_fixed = BATCH_KCHUNK;
+        const Problem& p = L.prob[i];
+        const double* A = dA_base ? dA_base + hd[i].a_offset : nullptr;
+        const double* b = db_base ? db_base + hd[i].b_offset : nullptr;
+        double* x = dx_base ? dx_base + hd[i].x_offset : nullptr;
+        pne_status rc = run_precond(ex, p, A, o->seed, (uint32_t)i, sk[i], qr[i], L.buf[i], dinfo ? dinfo + i : nullptr);
+        if (rc) return rc;
+        rc = run_solve(ex, p, A, b, x, L.buf[i], dinfo ? dinfo + i : nullptr);
+        if (rc) return rc;
+    }
+    return PNE_OK;
+}
+
+pne_status record_condest(Recorder& rec, int64_t batch, const pne_problem_desc* hd, const double* dA_base,
+                          const pne_opts* o, const BatchLayout& L)
+{
+    for (int64_t i = 0; i < batch; ++i) {
+        Exec ex;
+        ex.rec = &rec;
+        ex.member = (int32_t)i;
+        ex.kchunk_fixed = BATCH_KCHUNK;
+        const Problem& p = L.prob[i];
+        const Buffers& b = L.buf[i];
+        int rc = condest_run(ex, p.m, p.n, dA_base ? dA_base + hd[i].a_offset : nullptr, p.lda, o->known_kappa,
+                             b.k0, b.choice, b.scratch, scratch_cap_of(b));
+        if (rc) return (pne_status)rc;
+    }
+    return PNE_OK;
+}
+
+pne_status check_batch(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, int hpne)
+{
+    if (batch < 1 || batch > (1 << 24) || !hd || !o) return PNE_EINVAL;
+    for (int64_t i = 0; i < batch; ++i) {
+        const pne_problem_desc& d = hd[i];
+        pne_status chk = check_common(d.m, d.n, (const void*)1, d.lda, o);
+        if (chk) return chk;
+        if (d.a_offset < 0 || d.b_offset < 0 || d.x_offset < 0) return PNE_EINVAL;
+        if (hpne && !lu_supported(d.n)) return PNE_ENOTSUP;
+    }
+    return PNE_OK;
+}
+
+size_t batched_size(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, int hpne)
+{
+    if (check_batch(batch, hd, o, hpne) != PNE_OK) return 0;
+    // sizing pass: a placeholder base address (never dereferenced) gives the
+    // drivers non-null buffers with their real capacities
+    BatchLayout L;
+    batch_layout(batch, hd, o, hpne, (void*)(uintptr_t)0x100000, SIZE_MAX / 4, &L);
+    // table bound over every precision a member may use
+    int sk[3], qr[3], nsk, nqr;
+    candidates(o->sketch_prec, sk, &nsk);
+    candidates(o->qr_prec, qr, &nqr);
+    size_t tb = 0;
+    std::vector<int32_t> vs(batch), vq(batch);
+    for (int a = 0; a < nsk; ++a)
+        for (int c = 0; c < nqr; ++c) {
+            if (o->sketch_prec == PNE_PREC_AUTO && o->qr_prec == PNE_PREC_AUTO && a != c) continue;
+            for (int64_t i = 0; i < batch; ++i) { vs[i] = sk[a]; vq[i] = qr[c]; }
+            Recorder rec;
+            if (record_batch(rec, batch, hd, nullptr, nullptr, nullptr, o, L, vs.data(), vq.data(), nullptr))
+                return 0;
+            size_t b = table_bound(rec);
+            if (b > tb) tb = b;
+        }
+    if (batch_auto(o)) {
+        Recorder rec;
+        if (record_condest(rec, batch, hd, nullptr, o, L)) return 0;
+        size_t b = table_bound(rec);
+        if (b > tb) tb = b;
+    }
+    return L.fixed_bytes + tb;
+}
+
+pne_status solve_batched(int64_t batch, const pne_problem_desc* hd, const double* dA_base, const double* db_base,
+                         double* dx_base, const pne_opts* o, int hpne, void* dwork, size_t work_bytes,
+                         int32_t* dinfo, hipStream_t st)
+{
+    pne_status chk = check_batch(batch, hd, o, hpne);
+    if (chk) return chk;
+    if (!dA_base || !db_base || !dx_base || !dinfo || !dwork) return PNE_EINVAL;
+    if (work_bytes < batched_size(batch, hd, o, hpne)) return PNE_EWORKSPACE;
+    BatchLayout L;
+    batch_layout(batch, hd, o, hpne, dwork, work_bytes, &L);
+    prof_reset();
+    prof_mark(PH_START, st);
+    Exec ex0;
+    ex0.st = st;
+    zero_i32(ex0, batch, dinfo);
+    std::vector<int32_t> sk(batch, o->sketch_prec), qr(batch, o->qr_prec);
+    if (batch_auto(o)) {
+        Recorder rec;
+        pne_status rc = record_condest(rec, batch, hd, dA_base, o, L);
+        if (rc) return rc;
+        rc = (pne_status)run_recorded(rec, L.tables, L.table_cap, st);
+        if (rc) return rc;
+        std::vector<int32_t> ch(batch);
+        HIP_OK(hipMemcpyAsync(ch.data(), L.choice, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        for (int64_t i = 0; i < batch; ++i) {
+            if (sk[i] == PNE_PREC_AUTO) sk[i] = ch[i];
+            if (qr[i] == PNE_PREC_AUTO) qr[i] = ch[i];
+        }
+    }
+    prof_mark(PH_CONDEST, st);
+    Recorder rec;
+    pne_status rc = record_batch(rec, batch, hd, dA_base, db_base, dx_base, o, L, sk.data(), qr.data(), dinfo);
+    if (rc) return rc;
+    return (pne_status)run_recorded(rec, L.tables, L.table_cap, st);
 }
 
 }  // namespace
@@ -324,15 +533,17 @@ pne_status sketch_precond(int64_t m, int64_t n, const double* dA, int64_t lda, c
     Buffers b;
     const size_t need = layout(p, dwork, work_bytes, &b, true);
     if (work_bytes < need) return PNE_EWORKSPACE;
-    zero_i32(1, dinfo, st);
+    Exec ex;
+    ex.st = st;
+    zero_i32(ex, 1, dinfo);
     int sk, qr;
     float k0;
-    pne_status rc = resolve_precision(p, dA, o, b, scratch_cap_of(b), st, &sk, &qr, &k0);
+    pne_status rc = resolve_precision(ex, p, dA, o, b, scratch_cap_of(b), &sk, &qr, &k0);
     if (rc) return rc;
-    rc = run_precond(p, dA, o, sk, qr, b, dinfo, st);
+    rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
     if (rc) return rc;
-    for (int64_t j = 0; j < n; ++j)
-        HIP_OK(hipMemcpyAsync(dR + j * ldr, b.R + j * n, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    copy_f64(ex, n, n, b.R, n, dR, ldr);
+    if (hipGetLastError() != hipSuccess) return PNE_EHIP;
     if (hinfo) {
         hinfo->sketch_prec_used = sk;
         hinfo->qr_prec_used = qr;
@@ -355,8 +566,9 @@ pne_status cond_est(int64_t m, int64_t n, const double* dA, int64_t lda, float* 
     if (n < 1 || m < n || lda < m) return PNE_EINVAL;
     if (n > 4096) return PNE_ENOTSUP;
     if (work_bytes < condest_workspace_bytes(m, n)) return PNE_EWORKSPACE;
-    return (pne_status)condest_run(m, n, dA, lda, 0.0, dkappa0, dchoice, dwork, work_bytes,
-                                   (hipStream_t)stream);
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    return (pne_status)condest_run(ex, m, n, dA, lda, 0.0, dkappa0, dchoice, dwork, work_bytes);
 }
 
 size_t pne_sketch_workspace_size(int64_t m, int64_t n, int64_t s, int32_t prec)
@@ -376,44 +588,23 @@ pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64
     const int64_t br = block_rows > 0 ? block_rows : 128;
     if (scaled && br % 64 != 0) return PNE_EINVAL;
     if (work_bytes < sketch_workspace_bytes(m, n, s, prec, br)) return PNE_EWORKSPACE;
-    return (pne_status)sketch_run(m, n, dA, lda, s, seed, problem_id, prec, br, nullptr, 0, dAs, ldas,
-                                  dwork, work_bytes, (hipStream_t)stream);
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    return (pne_status)sketch_run(ex, m, n, dA, lda, s, seed, problem_id, prec, br, nullptr, 0, dAs, ldas,
+                                  dwork, work_bytes);
 }
 
 size_t pne_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* o, int hpne)
 {
-    if (batch < 1 || !hdesc || !o) return 0;
-    size_t best = 0;
-    for (int64_t i = 0; i < batch; ++i) {
-        size_t b = pne_workspace_size(hdesc[i].m, hdesc[i].n, o, hpne);
-        if (b == 0) return 0;
-        if (b > best) best = b;
-    }
-    return best;
+    return batched_size(batch, hdesc, o, hpne);
 }
 
 pne_status pne_solve_batched(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
                              const double* db_base, double* dx_base, const pne_opts* o, int hpne,
                              void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream)
 {
-    if (batch < 1 || !hdesc || !dA_base || !db_base || !dx_base || !o || !dinfo || !dwork) return PNE_EINVAL;
-    for (int64_t i = 0; i < batch; ++i) {
-        const pne_problem_desc& d = hdesc[i];
-        pne_status chk = check_common(d.m, d.n, dA_base, d.lda, o);
-        if (chk) return chk;
-        if (d.a_offset < 0 || d.b_offset < 0 || d.x_offset < 0) return PNE_EINVAL;
-    }
-    if (work_bytes < pne_batched_workspace_size(batch, hdesc, o, hpne)) return PNE_EWORKSPACE;
-    for (int64_t i = 0; i < batch; ++i) {
-        const pne_problem_desc& d = hdesc[i];
-        pne_opts oi = *o;
-        oi.problem_id = (uint32_t)i;
-        pne_status rc = solve_impl(hpne, d.m, d.n, dA_base + d.a_offset, d.lda, db_base + d.b_offset,
-                                   dx_base + d.x_offset, &oi, dwork, work_bytes, dinfo + i, nullptr,
-                                   (hipStream_t)stream);
-        if (rc) return rc;
-    }
-    return PNE_OK;
+    return solve_batched(batch, hdesc, dA_base, db_base, dx_base, o, hpne, dwork, work_bytes, dinfo,
+                         (hipStream_t)stream);
 }
 
 }  // extern "C"

@@ -8,6 +8,7 @@
 // 2000 + k + 1 (first failure only) and the factor continues as NaN.
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pne {
 
@@ -51,44 +52,58 @@ struct CholSteps<T, CB> {
     static __device__ __forceinline__ void run(int, T (&)[16], T*, int32_t*, int64_t) {}
 };
 
+struct PotrfDiagArgs {
+    int w;
+    void* C;
+    int64_t ldc;
+    int32_t* info;
+    int64_t c0;
+};
 template <typename T>
-__global__ __launch_bounds__(256) void potrf_diag_kernel(int w, T* __restrict__ C, int64_t ldc,
-                                                         int32_t* __restrict__ info, int64_t c0)
+struct PotrfDiag {
+    typedef PotrfDiagArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const PotrfDiagArgs& a, int, int)
+    {
+        const int w = a.w;
+        const int64_t ldc = a.ldc;
+        T* __restrict__ C = (T*)a.C;
+        __shared__ T lcol[CB];
+        const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+        T v[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int j = 16 * q + t;
+            v[t] = (lane < w && j < w && lane >= j) ? C[lane + (int64_t)j * ldc] : (T)0;
+        }
+        CholSteps<T, 0>::run(w, v, lcol, a.info, a.c0);
+#pragma unroll
+        for (int t = 0; t < 16; ++t) {
+            const int j = 16 * q + t;
+            if (lane < w && j < w) C[lane + (int64_t)j * ldc] = (lane >= j) ? v[t] : (T)0;
+        }
+    }
+};
+
+template <typename T>
+static void gemm_t(Exec& ex, const GemmArgs& g)
 {
-    __shared__ T lcol[CB];
-    const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
-    T a[16];
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int j = 16 * q + t;
-        a[t] = (lane < w && j < w && lane >= j) ? C[lane + (int64_t)j * ldc] : (T)0;
-    }
-    CholSteps<T, 0>::run(w, a, lcol, info, c0);
-#pragma unroll
-    for (int t = 0; t < 16; ++t) {
-        const int j = 16 * q + t;
-        if (lane < w && j < w) C[lane + (int64_t)j * ldc] = (lane >= j) ? a[t] : (T)0;
-    }
+    if constexpr (sizeof(T) == 8) gemm_f64(ex, g);
+    else gemm_f32(ex, g);
 }
 
 template <typename T>
-static void gemm_t(const GemmArgs& g, hipStream_t st)
-{
-    if constexpr (sizeof(T) == 8) gemm_f64(g, st);
-    else gemm_f32(g, st);
-}
-
-template <typename T>
-void cholesky(int64_t n, T* C, int64_t ldc, int32_t* info, hipStream_t st)
+void cholesky(Exec& ex, int64_t n, T* C, int64_t ldc, int32_t* info)
 {
     for (int64_t c0 = 0; c0 < n; c0 += CB) {
+        ex.iter((uint32_t)(c0 / CB));
         const int w = (int)((n - c0 < CB) ? n - c0 : CB);
         T* D = C + c0 + c0 * ldc;
-        potrf_diag_kernel<T><<<1, 256, 0, st>>>(w, D, ldc, info, c0);
+        launch<PotrfDiag<T>>(ex, 1, 1, PotrfDiagArgs{w, D, ldc, info, c0});
         const int64_t rem = n - c0 - w;
         if (rem <= 0) break;
         T* X = C + (c0 + w) + c0 * ldc;
-        trsm_leaf<T, true, false>(rem, w, X, 1, ldc, D, ldc, st);
+        trsm_leaf<T, true, false>(ex, rem, w, X, 1, ldc, D, ldc);
         T* C22 = C + (c0 + w) + (c0 + w) * ldc;
         GemmArgs g{};
         g.M = rem; g.N = rem; g.K = w;
@@ -97,10 +112,10 @@ void cholesky(int64_t n, T* C, int64_t ldc, int32_t* info, hipStream_t st)
         g.alpha = -1.0; g.beta = 1.0;
         g.Cin = C22; g.ldcin = ldc; g.C = C22; g.ldc = ldc;
         g.lower = 1; g.splits = 1;
-        gemm_t<T>(g, st);
+        gemm_t<T>(ex, g);
     }
 }
-template void cholesky<double>(int64_t, double*, int64_t, int32_t*, hipStream_t);
-template void cholesky<float>(int64_t, float*, int64_t, int32_t*, hipStream_t);
+template void cholesky<double>(Exec&, int64_t, double*, int64_t, int32_t*);
+template void cholesky<float>(Exec&, int64_t, float*, int64_t, int32_t*);
 
 }  // namespace pne

@@ -19,6 +19,7 @@
 // Section 6.4).
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 #include "trsv_dev.h"
 
 namespace pne {
@@ -31,20 +32,40 @@ __device__ __forceinline__ int32_t pick_precision(float k0)
     return PNE_PREC_FP64;
 }
 
-__global__ void known_kappa_kernel(double known_kappa, float* k0, int32_t* choice)
-{
-    if (threadIdx.x == 0) {
-        const float v = (float)log10(known_kappa);
-        *k0 = v;
-        *choice = pick_precision(v);
+struct KnownKappa {
+    struct Args {
+        double known_kappa;
+        float* k0;
+        int32_t* choice;
+    };
+    static constexpr int NTH = 64, WPE = 0;
+    static __device__ void run(const Args& a, int, int)
+    {
+        if (threadIdx.x == 0) {
+            const float v = (float)log10(a.known_kappa);
+            *a.k0 = v;
+            *a.choice = pick_precision(v);
+        }
     }
-}
+};
 
 // ||G||_1 from the lower triangle of the symmetric G (column j sums |G(i,j)|
 // for i >= j and |G(j,i)| for i < j).
-__global__ __launch_bounds__(1024) void norm1_sym_kernel(int64_t n, const float* __restrict__ G, int64_t ld,
-                                                          float* __restrict__ out)
+struct Norm1Sym {
+    struct Args {
+        int64_t n;
+        const float* G;
+        int64_t ld;
+        float* out;
+    };
+    static constexpr int NTH = 1024, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+__device__ void Norm1Sym::run(const Args& a, int, int)
 {
+    const int64_t n = a.n, ld = a.ld;
+    const float* __restrict__ G = a.G;
+    float* __restrict__ out = a.out;
     __shared__ float red[16];
     float best = 0.0f;
     for (int64_t j = threadIdx.x; j < n; j += 1024) {
@@ -62,16 +83,30 @@ __global__ __launch_bounds__(1024) void norm1_sym_kernel(int64_t n, const float*
     }
 }
 
-__global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __restrict__ L, int64_t ld,
-                                                     const float* __restrict__ DL,
-                                                     const float* __restrict__ g1,
-                                                     const int32_t* __restrict__ info,
-                                                     float* __restrict__ k0, int32_t* __restrict__ choice)
+struct Hager {
+    struct Args {
+        int64_t n;
+        const float* L;
+        int64_t ld;
+        const float* DL;
+        const float* g1;
+        const int32_t* info;
+        float* k0;
+        int32_t* choice;
+    };
+    static constexpr int NTH = 1024, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+__device__ void Hager::run(const Args& a, int, int)
 {
-    extern __shared__ unsigned char smem[];
-    float* x = (float*)smem;
-    float* y = x + n;
-    float* z = y + n;
+    const int64_t n = a.n, ld = a.ld;
+    const float* __restrict__ L = a.L;
+    const float* __restrict__ DL = a.DL;
+    const float* __restrict__ g1 = a.g1;
+    const int32_t* __restrict__ info = a.info;
+    float* __restrict__ k0 = a.k0;
+    int32_t* __restrict__ choice = a.choice;
+    __shared__ float x[4096], y[4096], z[4096];
     __shared__ float redf[16];
     __shared__ float tmp[TB];
     __shared__ float redz[16], redd[16];
@@ -142,16 +177,16 @@ __global__ __launch_bounds__(1024) void hager_kernel(int64_t n, const float* __r
 struct CePlan {
     int64_t splits, kchunk;
 };
-static CePlan ce_plan(int64_t m, int64_t n)
+static CePlan ce_plan(int64_t m, int64_t n, int64_t kchunk_fixed)
 {
     CePlan p;
-    plan_splitk(m, gemm_tiles(n, n, 1, 128), &p.splits, &p.kchunk);
+    plan_splitk(m, gemm_tiles(n, n, 1, 128), &p.splits, &p.kchunk, kchunk_fixed);
     return p;
 }
 
-size_t condest_workspace_bytes(int64_t m, int64_t n)
+size_t condest_workspace_bytes(int64_t m, int64_t n, int64_t kchunk_fixed)
 {
-    CePlan p = ce_plan(m, n);
+    CePlan p = ce_plan(m, n, kchunk_fixed);
     Arena ar(nullptr, 0);
     ar.take<float>((size_t)n * n);              // G / L
     ar.take<float>((size_t)p.splits * n * n);   // SYRK partials
@@ -161,23 +196,24 @@ size_t condest_workspace_bytes(int64_t m, int64_t n)
     return ar.used;
 }
 
-int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
-                int32_t* dchoice, void* work, size_t work_bytes, hipStream_t st)
+int condest_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
+                int32_t* dchoice, void* work, size_t work_bytes)
 {
+    ex.stage(ST_CONDEST_GRAM);
     if (known_kappa > 0.0) {
-        known_kappa_kernel<<<1, 64, 0, st>>>(known_kappa, dk0, dchoice);
-        return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+        launch<KnownKappa>(ex, 1, 1, KnownKappa::Args{known_kappa, dk0, dchoice});
+        return launch_status(ex);
     }
-    if (work_bytes < condest_workspace_bytes(m, n)) return PNE_EWORKSPACE;
+    if (work_bytes < condest_workspace_bytes(m, n, ex.kchunk_fixed)) return PNE_EWORKSPACE;
     if (n > 4096) return PNE_ENOTSUP;
-    CePlan p = ce_plan(m, n);
+    CePlan p = ce_plan(m, n, ex.kchunk_fixed);
     Arena ar(work, work_bytes);
     float* G = ar.take<float>((size_t)n * n);
     float* P = ar.take<float>((size_t)p.splits * n * n);
     float* g1 = ar.take<float>(4);
     int32_t* info = ar.take<int32_t>(4);
     float* DL = ar.take<float>(dinv_elems(n));
-    zero_i32(1, info, st);
+    zero_i32(ex, 1, info);
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;
     g.A = A; g.lda = lda; g.transA = 1;
@@ -186,12 +222,15 @@ int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known
     g.C = G; g.ldc = n;
     g.lower = 1;
     g.splits = p.splits; g.kchunk = p.kchunk; g.P = P;
-    gemm_ddf(g, st);
-    norm1_sym_kernel<<<1, 1024, 0, st>>>(n, G, n, g1);
-    cholesky<float>(n, G, n, info, st);
-    inv_diag_blocks<float>(n, G, n, 1, 0, 0, DL, st);
-    hager_kernel<<<1, 1024, 3 * n * sizeof(float), st>>>(n, G, n, DL, g1, info, dk0, dchoice);
-    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+    gemm_ddf(ex, g);
+    launch<Norm1Sym>(ex, 1, 1, Norm1Sym::Args{n, G, n, g1});
+    ex.stage(ST_CONDEST_FACTOR);
+    cholesky<float>(ex, n, G, n, info);
+    ex.stage(ST_CONDEST_INV);
+    inv_diag_blocks<float>(ex, n, G, n, 1, 0, 0, DL);
+    ex.stage(ST_CONDEST_EST);
+    launch<Hager>(ex, 1, 1, Hager::Args{n, G, n, DL, g1, info, dk0, dchoice});
+    return launch_status(ex);
 }
 
 }  // namespace pne

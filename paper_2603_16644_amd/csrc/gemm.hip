@@ -14,6 +14,7 @@
 // kernel reduces in a fixed order.
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pne {
 
@@ -37,7 +38,14 @@ __device__ __forceinline__ void lower_tile(int64_t id, int64_t& ti, int64_t& tj)
 }
 
 template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void gemm_cm_kernel(GemmArgs g)
+struct GemmCm {
+    typedef GemmArgs Args;
+    static constexpr int NTH = 256, WPE = 2;
+    static __device__ void run(const GemmArgs& g, int bx, int by);
+};
+
+template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
+__device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, int by)
 {
     typedef typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type VC;
     constexpr int TN = BN / 32;                // 16-wide MFMA tiles per wave along N
@@ -54,10 +62,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
     int64_t ti, tj;
     const int64_t tiles_m = (g.M + G_BM - 1) / G_BM;
-    if (g.lower) lower_tile(blockIdx.x, ti, tj);
-    else { ti = blockIdx.x % tiles_m; tj = blockIdx.x / tiles_m; }
+    if (g.lower) lower_tile(bx, ti, tj);
+    else { ti = bx % tiles_m; tj = bx / tiles_m; }
     const int64_t i0 = ti * G_BM, j0 = tj * BN;
-    const int64_t kbeg = PARTIAL ? (int64_t)blockIdx.y * g.kchunk : 0;
+    const int64_t kbeg = PARTIAL ? (int64_t)by * g.kchunk : 0;
     int64_t kend = PARTIAL ? kbeg + g.kchunk : g.K;
     if (kend > g.K) kend = g.K;
 
@@ -228,7 +236,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     // the loads are not serialised behind stores one by one.
     TC* C = (TC*)g.C;
     const TC* Cin = (const TC*)g.Cin;
-    TC* P = PARTIAL ? (TC*)g.P + (int64_t)blockIdx.y * g.M * g.N : nullptr;
+    TC* P = PARTIAL ? (TC*)g.P + (int64_t)by * g.M * g.N : nullptr;
     const TC* src = PARTIAL ? (g.accumulate_partials ? P : nullptr) : Cin;
     const int64_t lds_ = PARTIAL ? g.M : g.ldcin;
 #pragma unroll
@@ -257,15 +265,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
             }
     }
     if (fold && tid < G_BM && i0 + tid < g.M) {
-        if (PARTIAL) ((TC*)g.Pc)[(int64_t)blockIdx.y * g.M + i0 + tid] = cpart;
+        if (PARTIAL) ((TC*)g.Pc)[(int64_t)by * g.M + i0 + tid] = cpart;
         else ((TC*)g.cvec)[i0 + tid] = cpart;
     }
 }
 
+struct GemmReduceArgs {
+    GemmArgs g;
+    int bn;
+};
 template <typename TC>
-__global__ __launch_bounds__(256) void gemm_reduce_kernel(GemmArgs g, int bn)
+struct GemmReduce {
+    typedef GemmReduceArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+template <typename TC>
+__device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
 {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const GemmArgs& g = a.g;
+    const int bn = a.bn;
+    const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     const TC* P = (const TC*)g.P;
     if (idx < g.M * g.N) {
         const int64_t i = idx % g.M, j = idx / g.M;
@@ -291,12 +311,20 @@ int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn)
     return tm * tn;
 }
 
-// Split-K plan for a product with `tiles` output tiles: the number of splits
-// (chunks of at least 128 along K) whose work-group count fills whole waves of
-// the machine best (256 CUs x 2 resident work-groups), preferring more
-// work-groups when the fill is equal.
-void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk)
+// Split-K plan for a product with `tiles` output tiles.  Alone on the
+// machine: the number of splits (chunks of at least 128 along K) whose
+// work-group count fills whole waves of the machine best (256 CUs x 2
+// resident work-groups), preferring more work-groups when the fill is equal.
+// In a batch (kchunk_fixed > 0) every product is cut into chunks of a fixed
+// length instead, so that work-groups carry similar work across members.
+void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int64_t kchunk_fixed)
 {
+    if (kchunk_fixed > 0) {
+        const int64_t kc = ceil_div(kchunk_fixed < K ? kchunk_fixed : K, G_BK) * G_BK;
+        *kchunk = kc > 0 ? kc : G_BK;
+        *splits = K > 0 ? ceil_div(K, *kchunk) : 1;
+        return;
+    }
     const int64_t slots = 512;
     if (tiles < 1) tiles = 1;
     int64_t maxs = K / 128;
@@ -316,8 +344,16 @@ void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk)
     *splits = ceil_div(K, kc);
 }
 
+template <typename TC>
+static void gemm_reduce_launch(Exec& ex, const GemmArgs& g, int bn)
+{
+    int64_t cnt = g.M * g.N;
+    if (g.bvec && g.M > cnt) cnt = g.M;
+    launch<GemmReduce<TC>>(ex, ceil_div(cnt, 256), 1, GemmReduceArgs{g, bn});
+}
+
 template <typename TA, typename TB, typename TC>
-static void gemm_launch(const GemmArgs& g0, hipStream_t st, bool reduce)
+static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
 {
     GemmArgs g = g0;
     const bool narrow = !g.lower && g.N <= 64;
@@ -327,39 +363,22 @@ static void gemm_launch(const GemmArgs& g0, hipStream_t st, bool reduce)
     const bool partial = g.splits > 1 || !reduce;
     if (!partial) {
         g.splits = 1;
-        dim3 grid(tiles, 1);
-        if (narrow) gemm_cm_kernel<TA, TB, TC, 64, false><<<grid, 256, 0, st>>>(g);
-        else gemm_cm_kernel<TA, TB, TC, 128, false><<<grid, 256, 0, st>>>(g);
+        if (narrow) launch<GemmCm<TA, TB, TC, 64, false>>(ex, tiles, 1, g);
+        else launch<GemmCm<TA, TB, TC, 128, false>>(ex, tiles, 1, g);
         return;
     }
     if (g.splits < 1) g.splits = 1;
     if (g.kchunk <= 0) g.kchunk = ceil_div(ceil_div(g.K, g.splits), G_BK) * G_BK;
-    dim3 grid(tiles, g.splits);
-    if (narrow) gemm_cm_kernel<TA, TB, TC, 64, true><<<grid, 256, 0, st>>>(g);
-    else gemm_cm_kernel<TA, TB, TC, 128, true><<<grid, 256, 0, st>>>(g);
-    if (reduce) {
-        int64_t cnt = g.M * g.N;
-        if (g.bvec && g.M > cnt) cnt = g.M;
-        gemm_reduce_kernel<TC><<<ceil_div(cnt, 256), 256, 0, st>>>(g, bn);
-    }
+    if (narrow) launch<GemmCm<TA, TB, TC, 64, true>>(ex, tiles, g.splits, g);
+    else launch<GemmCm<TA, TB, TC, 128, true>>(ex, tiles, g.splits, g);
+    if (reduce) gemm_reduce_launch<TC>(ex, g, bn);
 }
 
-void gemm_f64(const GemmArgs& g, hipStream_t st) { gemm_launch<double, double, double>(g, st, true); }
-void gemm_f64_reduce(const GemmArgs& g, hipStream_t st)
-{
-    int64_t cnt = g.M * g.N;
-    if (g.bvec && g.M > cnt) cnt = g.M;
-    gemm_reduce_kernel<double><<<ceil_div(cnt, 256), 256, 0, st>>>(g, 128);
-}
-void gemm_f64_partials(const GemmArgs& g, hipStream_t st)
-{
-    gemm_launch<double, double, double>(g, st, false);
-}
-void gemm_f32(const GemmArgs& g, hipStream_t st) { gemm_launch<float, float, float>(g, st, true); }
-void gemm_f32_partials(const GemmArgs& g, hipStream_t st)
-{
-    gemm_launch<float, float, float>(g, st, false);
-}
-void gemm_ddf(const GemmArgs& g, hipStream_t st) { gemm_launch<double, double, float>(g, st, true); }
+void gemm_f64(Exec& ex, const GemmArgs& g) { gemm_launch<double, double, double>(ex, g, true); }
+void gemm_f64_reduce(Exec& ex, const GemmArgs& g) { gemm_reduce_launch<double>(ex, g, 128); }
+void gemm_f64_partials(Exec& ex, const GemmArgs& g) { gemm_launch<double, double, double>(ex, g, false); }
+void gemm_f32(Exec& ex, const GemmArgs& g) { gemm_launch<float, float, float>(ex, g, true); }
+void gemm_f32_partials(Exec& ex, const GemmArgs& g) { gemm_launch<float, float, float>(ex, g, false); }
+void gemm_ddf(Exec& ex, const GemmArgs& g) { gemm_launch<double, double, float>(ex, g, true); }
 
 }  // namespace pne

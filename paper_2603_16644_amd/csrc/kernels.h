@@ -4,6 +4,7 @@
 #include <stdint.h>
 
 #include "common.h"
+#include "launch.h"
 
 namespace pne {
 
@@ -37,11 +38,14 @@ struct SketchPlan {
     int64_t chunk, nchunks, ldk, splits, kchunk;
     size_t bytes;
 };
-SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br);
-size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br);
-int sketch_run(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+// kchunk_fixed > 0: split the product over rows of A in chunks of this
+// length (batches) instead of filling the machine with one sketch
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br, int64_t kchunk_fixed = 0);
+size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br,
+                              int64_t kchunk_fixed = 0);
+int sketch_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
                uint32_t pid, int prec, int64_t br, float* As32, int64_t ld32, double* As64,
-               int64_t ld64, void* work, size_t work_bytes, hipStream_t st);
+               int64_t ld64, void* work, size_t work_bytes);
 
 // ---------------------------------------------------------------- GEMM
 // Column-major C = alpha op(A) op(B) + beta Cin (C may alias Cin).
@@ -63,70 +67,73 @@ struct GemmArgs {
     const void* bvec; void* Pc; void* cvec;
 };
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
-void gemm_f64(const GemmArgs& g, hipStream_t st);           // full path incl. reduce
-void gemm_f64_partials(const GemmArgs& g, hipStream_t st);  // partials only (no reduce)
-void gemm_f64_reduce(const GemmArgs& g, hipStream_t st);    // reduce of the partials (bn = 128)
-void gemm_f32(const GemmArgs& g, hipStream_t st);
-void gemm_f32_partials(const GemmArgs& g, hipStream_t st);
-void gemm_ddf(const GemmArgs& g, hipStream_t st);           // fl32(A)^T fl32(B) etc.
-// split-K plan: splits and kchunk for a long-K product with `tiles` output tiles
-void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk);
+void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce
+void gemm_f64_partials(Exec& ex, const GemmArgs& g);  // partials only (no reduce)
+void gemm_f64_reduce(Exec& ex, const GemmArgs& g);    // reduce of the partials (bn = 128)
+void gemm_f32(Exec& ex, const GemmArgs& g);
+void gemm_f32_partials(Exec& ex, const GemmArgs& g);
+void gemm_ddf(Exec& ex, const GemmArgs& g);           // fl32(A)^T fl32(B) etc.
+// split-K plan: splits and kchunk for a long-K product with `tiles` output
+// tiles (kchunk_fixed > 0: fixed chunk length, for batches)
+void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int64_t kchunk_fixed = 0);
 int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn);
 
 // ---------------------------------------------------------------- TRSM / factorizations
 // Ap = A R^{-1}, R upper n x n (FP64), blocked substitution.
-void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
-                      int64_t ldr, double* Ap, int64_t ldap, hipStream_t st);
+void trsm_right_upper(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
+                      int64_t ldr, double* Ap, int64_t ldap);
 // row-parallel substitution on a block of <= 64 columns: X := X R^{-1}
 // (R upper, TL = false) or X := X L^{-T} (L lower, TL = true); element
 // (i, c) of X at X[i*rs + c*cs]; UNIT: unit diagonal
 template <typename T, bool TL, bool UNIT>
-void trsm_leaf(int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr, hipStream_t st);
+void trsm_leaf(Exec& ex, int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr);
 // Cholesky (lower, in place) of the n x n matrix C; info word gets 2000+k.
 template <typename T>
-void cholesky(int64_t n, T* C, int64_t ldc, int32_t* info, hipStream_t st);
+void cholesky(Exec& ex, int64_t n, T* C, int64_t ldc, int32_t* info);
 // LU with partial pivoting in place; piv 0-based; info 3000+k.
-void lu_factor(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, hipStream_t st);
+void lu_factor(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info);
 // Householder QR (R only) of the s x n matrix W (in place); R (FP64, n x n,
 // upper, ldr) rounded to qr_prec; info 1000+k for a zero diagonal.
 size_t qr_workspace_bytes(int64_t s, int64_t n, int prec);
-int qr_r(int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr, int32_t* info,
-         void* work, size_t work_bytes, hipStream_t st);
+int qr_r(Exec& ex, int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr,
+         int32_t* info, void* work, size_t work_bytes);
 bool qr_supported(int64_t s, int prec);
 
 // ---------------------------------------------------------------- vectors
-// triangular solve with one work-group: x := op(T)^{-1} x
-// uplo: 0 lower, 1 upper; trans: 0 T, 1 T^T; unit: unit diagonal
-template <typename T>
-void trsv(int64_t n, const T* M, int64_t ld, int uplo, int trans, int unit, T* x, hipStream_t st);
 // inverses of the 64 x 64 diagonal blocks of op(M) (dinv_elems(n) values)
 size_t dinv_elems(int64_t n);
 template <typename T>
-void inv_diag_blocks(int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv, hipStream_t st);
+void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv);
 // x = U^{-1} L^{-1} P c (c and x may alias); DL, DU: block inverses of the
 // unit lower L and of U
-void lu_solve2(int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL, const double* DU,
-               const double* c, double* x, hipStream_t st);
+void lu_solve2(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
+               const double* DU, const double* c, double* x);
 // x = R^{-1} L^{-T} L^{-1} c (PNE: Cholesky factor L, preconditioner R) with
 // the block inverses DL of L and DR of R
-void pne_solve3(int64_t n, const double* L, int64_t ldl, const double* DL, const double* R, int64_t ldr,
-                const double* DR, const double* c, double* x, hipStream_t st);
+void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* R,
+                int64_t ldr, const double* DR, const double* c, double* x);
 bool lu_supported(int64_t n);
 // r = b - A x
-void residual(int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,
-              double* r, hipStream_t st);
+void residual(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,
+              double* r);
 // y = X^T v (X m x n), split over m with partials P (splits x n)
 size_t gemv_t_partials(int64_t m, int64_t n);
-void gemv_t(int64_t m, int64_t n, const double* X, int64_t ldx, const double* v, double* y,
-            double* P, hipStream_t st);
-void axpy_update(int64_t n, double* x, const double* d, hipStream_t st);   // x += d
-void fill_nan_on_info(int64_t n, double* x, const int32_t* info, hipStream_t st);
-void copy_f64(int64_t n, const double* src, double* dst, hipStream_t st);
-void zero_i32(int64_t n, int32_t* p, hipStream_t st);
+void gemv_t(Exec& ex, int64_t m, int64_t n, const double* X, int64_t ldx, const double* v, double* y,
+            double* P);
+void axpy_update(Exec& ex, int64_t n, double* x, const double* d);   // x += d
+void fill_nan_on_info(Exec& ex, int64_t n, double* x, const int32_t* info);
+// dst(:, j) = src(:, j) for an r x c column-major block
+void copy_f64(Exec& ex, int64_t r, int64_t c, const double* src, int64_t lds, double* dst, int64_t ldd);
+void zero_i32(Exec& ex, int64_t n, int32_t* p);
+
+// ---------------------------------------------------------------- batches
+// Merge the recorded launches of a batch into grouped launches, copy their
+// tables to dtables (cap bytes) and enqueue them on st (batched.hip).
+int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st);
 
 // ---------------------------------------------------------------- condition estimate
-size_t condest_workspace_bytes(int64_t m, int64_t n);
-int condest_run(int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
-                int32_t* dchoice, void* work, size_t work_bytes, hipStream_t st);
+size_t condest_workspace_bytes(int64_t m, int64_t n, int64_t kchunk_fixed = 0);
+int condest_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
+                int32_t* dchoice, void* work, size_t work_bytes);
 
 }  // namespace pne

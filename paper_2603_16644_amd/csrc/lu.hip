@@ -12,17 +12,36 @@
 // A zero pivot at global column k sets *info = 3000 + k + 1 (first only).
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pne {
 
 constexpr int LU_THREADS = 512;
 constexpr int LU_WAVES = LU_THREADS / 64;
 
+struct LuPanelArgs {
+    int64_t h;
+    int w;
+    double* P;
+    int64_t ldc;
+    int32_t* piv;
+    int64_t c0;
+    int32_t* info;
+};
 template <int RPT, int PW>
-__global__ __launch_bounds__(LU_THREADS) void lu_panel_kernel(int64_t h, int w, double* __restrict__ P,
-                                                        int64_t ldc, int32_t* __restrict__ piv,
-                                                        int64_t c0, int32_t* __restrict__ info)
+struct LuPanel {
+    typedef LuPanelArgs Args;
+    static constexpr int NTH = LU_THREADS, WPE = 0;
+    static __device__ void run(const LuPanelArgs& a, int bx, int by);
+};
+template <int RPT, int PW>
+__device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 {
+    const int64_t h = a.h, ldc = a.ldc, c0 = a.c0;
+    const int w = a.w;
+    double* __restrict__ P = a.P;
+    int32_t* __restrict__ piv = a.piv;
+    int32_t* __restrict__ info = a.info;
     __shared__ double rowK[PW], rowP[PW];
     __shared__ double wv[LU_WAVES];
     __shared__ int64_t wi[LU_WAVES];
@@ -122,11 +141,25 @@ __global__ __launch_bounds__(LU_THREADS) void lu_panel_kernel(int64_t h, int w, 
 }
 
 // Apply the panel's row exchanges to every column outside [c0, c0 + w).
-__global__ __launch_bounds__(256) void lu_swap_kernel(int64_t n, double* __restrict__ C, int64_t ldc,
-                                                      const int32_t* __restrict__ piv, int64_t c0,
-                                                      int w)
+struct LuSwap {
+    struct Args {
+        int64_t n;
+        double* C;
+        int64_t ldc;
+        const int32_t* piv;
+        int64_t c0;
+        int w;
+    };
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+__device__ void LuSwap::run(const Args& a, int bx, int)
 {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = a.n, ldc = a.ldc, c0 = a.c0;
+    const int w = a.w;
+    double* __restrict__ C = a.C;
+    const int32_t* __restrict__ piv = a.piv;
+    const int64_t j = (int64_t)bx * 256 + threadIdx.x;
     if (j >= n || (j >= c0 && j < c0 + w)) return;
     double* col = C + j * ldc;
     for (int k = 0; k < w; ++k) {
@@ -137,19 +170,19 @@ __global__ __launch_bounds__(256) void lu_swap_kernel(int64_t n, double* __restr
 }
 
 template <int RPT, int PW>
-static void lu_steps(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, int64_t c0,
-                     hipStream_t st)
+static void lu_steps(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, int64_t c0)
 {
+    ex.iter((uint32_t)c0);
     const int w = (int)((n - c0 < PW) ? n - c0 : PW);
     const int64_t h = n - c0;
-    lu_panel_kernel<RPT, PW><<<1, LU_THREADS, 0, st>>>(h, w, C + c0 + c0 * ldc, ldc, piv, c0, info);
-    lu_swap_kernel<<<ceil_div(n, 256), 256, 0, st>>>(n, C, ldc, piv, c0, w);
+    launch<LuPanel<RPT, PW>>(ex, 1, 1, LuPanelArgs{h, w, C + c0 + c0 * ldc, ldc, piv, c0, info});
+    launch<LuSwap>(ex, ceil_div(n, 256), 1, LuSwap::Args{n, C, ldc, piv, c0, w});
     const int64_t rem = n - c0 - w;
     if (rem <= 0) return;
     double* C12 = C + c0 + (c0 + w) * ldc;
     // U12^T L11^T = C12^T: row j of U12^T is column j of C12 (stride 1 along
     // the row, ldc between rows)
-    trsm_leaf<double, true, true>(rem, w, C12, ldc, 1, C + c0 + c0 * ldc, ldc, st);
+    trsm_leaf<double, true, true>(ex, rem, w, C12, ldc, 1, C + c0 + c0 * ldc, ldc);
     GemmArgs g{};
     g.M = rem; g.N = rem; g.K = w;
     g.A = C + (c0 + w) + c0 * ldc; g.lda = ldc; g.transA = 0;
@@ -158,20 +191,20 @@ static void lu_steps(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* i
     double* C22 = C + (c0 + w) + (c0 + w) * ldc;
     g.Cin = C22; g.ldcin = ldc; g.C = C22; g.ldc = ldc;
     g.splits = 1;
-    gemm_f64(g, st);
+    gemm_f64(ex, g);
 }
 
 bool lu_supported(int64_t n) { return n <= 4096; }
 
-void lu_factor(int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info, hipStream_t st)
+void lu_factor(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info)
 {
     int64_t c0 = 0;
     while (c0 < n) {
         const int64_t h = n - c0;
-        if (h <= 512) { lu_steps<1, 32>(n, C, ldc, piv, info, c0, st); c0 += 32; }
-        else if (h <= 1024) { lu_steps<2, 32>(n, C, ldc, piv, info, c0, st); c0 += 32; }
-        else if (h <= 2048) { lu_steps<4, 16>(n, C, ldc, piv, info, c0, st); c0 += 16; }
-        else { lu_steps<8, 8>(n, C, ldc, piv, info, c0, st); c0 += 8; }
+        if (h <= 512) { lu_steps<1, 32>(ex, n, C, ldc, piv, info, c0); c0 += 32; }
+        else if (h <= 1024) { lu_steps<2, 32>(ex, n, C, ldc, piv, info, c0); c0 += 32; }
+        else if (h <= 2048) { lu_steps<4, 16>(ex, n, C, ldc, piv, info, c0); c0 += 16; }
+        else { lu_steps<8, 8>(ex, n, C, ldc, piv, info, c0); c0 += 8; }
     }
 }
 

@@ -17,6 +17,7 @@
 #include "common.h"
 #include "convert.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pne {
 
@@ -167,11 +168,29 @@ struct PanelSteps<T, NB, RPT, NT, NB> {
 // The column loop is unrolled (static register indices) for the shapes
 // where that keeps the panel free of register spills, and left rolled
 // otherwise (see QR_SHAPES).
+struct QrPanelArgs {
+    int64_t h;
+    int w;
+    void* W;
+    int64_t ldw;
+    void* V;
+    int64_t ldv;
+    void* Tout;
+};
 template <typename T, int NB, int RPT, int NT, bool UNROLL>
-__global__ __launch_bounds__(NT) void qr_panel_kernel(int64_t h, int w, T* __restrict__ W, int64_t ldw,
-                                                      T* __restrict__ V, int64_t ldv,
-                                                      T* __restrict__ Tout)
+struct QrPanel {
+    typedef QrPanelArgs Args;
+    static constexpr int NTH = NT, WPE = 0;
+    static __device__ void run(const QrPanelArgs& a, int bx, int by);
+};
+template <typename T, int NB, int RPT, int NT, bool UNROLL>
+__device__ void QrPanel<T, NB, RPT, NT, UNROLL>::run(const QrPanelArgs& a, int, int)
 {
+    const int64_t h = a.h, ldw = a.ldw, ldv = a.ldv;
+    const int w = a.w;
+    T* __restrict__ W = (T*)a.W;
+    T* __restrict__ V = (T*)a.V;
+    T* __restrict__ Tout = (T*)a.Tout;
     __shared__ PanelShared<T, NB, NT> sh;
     const int tid = threadIdx.x;
     for (int e = tid; e < NB * NB; e += NT) sh.Ts[e / NB][e % NB] = 0;
@@ -207,16 +226,33 @@ __global__ __launch_bounds__(NT) void qr_panel_kernel(int64_t h, int w, T* __res
 // P[z] is (rem x w, ld rem) = partial (W_trail^T V).  A work-group handles 16
 // columns: the split partials are summed by (column, entry) threads into LDS,
 // then each (column, entry) thread forms one entry of T^T y.
+struct QrTzArgs {
+    int64_t rem;
+    int w;
+    const void* P;
+    int64_t splits;
+    const void* Tm;
+    void* Z;
+};
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void qr_tz_kernel(int64_t rem, int w, const T* __restrict__ P,
-                                                    int64_t splits, const T* __restrict__ Tm,
-                                                    T* __restrict__ Z)
+struct QrTz {
+    typedef QrTzArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const QrTzArgs& a, int bx, int by);
+};
+template <typename T, int NB>
+__device__ void QrTz<T, NB>::run(const QrTzArgs& a, int bx, int)
 {
+    const int64_t rem = a.rem, splits = a.splits;
+    const int w = a.w;
+    const T* __restrict__ P = (const T*)a.P;
+    const T* __restrict__ Tm = (const T*)a.Tm;
+    T* __restrict__ Z = (T*)a.Z;
     __shared__ T Ts[NB * NB];
     __shared__ T ys[NB][16];
     for (int e = threadIdx.x; e < NB * NB; e += 256) Ts[e] = Tm[e];
     const int jl = threadIdx.x & 15;
-    const int64_t j = (int64_t)blockIdx.x * 16 + jl;
+    const int64_t j = (int64_t)bx * 16 + jl;
     for (int l = threadIdx.x >> 4; l < NB; l += 16) {
         T s = 0;
         if (j < rem && l < w)
@@ -232,11 +268,25 @@ __global__ __launch_bounds__(256) void qr_tz_kernel(int64_t rem, int w, const T*
     }
 }
 
+struct RoundMatrixArgs {
+    int64_t rows, cols;
+    void* M;
+    int64_t ld;
+    int prec;
+};
 template <typename T>
-__global__ __launch_bounds__(256) void round_matrix_kernel(int64_t rows, int64_t cols, T* M, int64_t ld,
-                                                           int prec)
+struct RoundMatrix {
+    typedef RoundMatrixArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const RoundMatrixArgs& a, int bx, int by);
+};
+template <typename T>
+__device__ void RoundMatrix<T>::run(const RoundMatrixArgs& a, int bx, int)
 {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t rows = a.rows, cols = a.cols, ld = a.ld;
+    const int prec = a.prec;
+    T* M = (T*)a.M;
+    const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     if (idx >= rows * cols) return;
     const int64_t i = idx % rows, j = idx / rows;
     float v = (float)M[i + j * ld];
@@ -247,11 +297,28 @@ __global__ __launch_bounds__(256) void round_matrix_kernel(int64_t rows, int64_t
 
 // R = upper triangle of W(0:n, 0:n) promoted to FP64 (rounded to BF16/FP16
 // first for those precisions).
+struct ExtractRArgs {
+    int64_t n;
+    const void* W;
+    int64_t ldw;
+    int prec;
+    double* R;
+    int64_t ldr;
+};
 template <typename T>
-__global__ __launch_bounds__(256) void extract_r_kernel(int64_t n, const T* __restrict__ W, int64_t ldw,
-                                                        int prec, double* __restrict__ R, int64_t ldr)
+struct ExtractR {
+    typedef ExtractRArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const ExtractRArgs& a, int bx, int by);
+};
+template <typename T>
+__device__ void ExtractR<T>::run(const ExtractRArgs& a, int bx, int)
 {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t n = a.n, ldw = a.ldw, ldr = a.ldr;
+    const int prec = a.prec;
+    const T* __restrict__ W = (const T*)a.W;
+    double* __restrict__ R = a.R;
+    const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     if (idx >= n * n) return;
     const int64_t i = idx % n, j = idx / n;
     double v = 0.0;
@@ -269,9 +336,21 @@ __global__ __launch_bounds__(256) void extract_r_kernel(int64_t n, const T* __re
 }
 
 // First zero on the diagonal of R -> *info = 1000 + k + 1 (if no earlier failure).
-__global__ __launch_bounds__(1024) void r_diag_check_kernel(int64_t n, const double* __restrict__ R,
-                                                            int64_t ldr, int32_t* __restrict__ info)
+struct RDiagCheck {
+    struct Args {
+        int64_t n;
+        const double* R;
+        int64_t ldr;
+        int32_t* info;
+    };
+    static constexpr int NTH = 1024, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+__device__ void RDiagCheck::run(const Args& a, int, int)
 {
+    const int64_t n = a.n, ldr = a.ldr;
+    const double* __restrict__ R = a.R;
+    int32_t* __restrict__ info = a.info;
     __shared__ int64_t wmin[16];
     int64_t mine = n;
     for (int64_t k = threadIdx.x; k < n; k += 1024)
@@ -322,37 +401,37 @@ size_t qr_workspace_bytes(int64_t s, int64_t n, int prec)
 }
 
 template <typename T, int NB, int RPT, int NT, bool U>
-static void panel_launch(int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm, hipStream_t st)
+static void panel_launch(Exec& ex, int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm)
 {
-    qr_panel_kernel<T, NB, RPT, NT, U><<<1, NT, 0, st>>>(h, w, Wp, ldw, V, ldv, Tm);
+    launch<QrPanel<T, NB, RPT, NT, U>>(ex, 1, 1, QrPanelArgs{h, w, Wp, ldw, V, ldv, Tm});
 }
 
 // Panel shapes (rows per thread, threads, unrolled column loop): the
 // smallest instantiation covering the panel height; unrolled only where the
 // compiled kernel is free of register spills.
 template <typename T, int NB>
-static void panel_dispatch(int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm, hipStream_t st)
+static void panel_dispatch(Exec& ex, int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm)
 {
     if constexpr (sizeof(T) == 4) {
-        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (h <= 2048) panel_launch<T, NB, 2, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else panel_launch<T, NB, 12, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 2048) panel_launch<T, NB, 2, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else panel_launch<T, NB, 12, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
     } else if constexpr (NB == 16) {
-        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else panel_launch<T, NB, 4, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else panel_launch<T, NB, 4, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
     } else {
-        if (h <= 2048) panel_launch<T, NB, 4, 512, true>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
-        else panel_launch<T, NB, 12, 512, false>(h, w, Wp, ldw, V, ldv, Tm, st);
+        if (h <= 2048) panel_launch<T, NB, 4, 512, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else panel_launch<T, NB, 12, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
     }
 }
 
 template <typename T>
-static int qr_run(int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, int64_t ldr,
-                  int32_t* info, void* work, size_t work_bytes, hipStream_t st)
+static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, int64_t ldr,
+                  int32_t* info, void* work, size_t work_bytes)
 {
     if (work_bytes < qr_bytes<T>(s, n)) return PNE_EWORKSPACE;
     const int NBv = qr_nb<T>(s);
@@ -363,32 +442,37 @@ static int qr_run(int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, 
     T* Tm = ar.take<T>((size_t)NBv * NBv);
     T* P = ar.take<T>((size_t)splits_max * n * NBv);
     T* Z = ar.take<T>((size_t)NBv * n);
+    ex.stage(ST_QR_ROUND);
     if constexpr (sizeof(T) == 4) {
         if (prec == PNE_PREC_BF16 || prec == PNE_PREC_FP16)
-            round_matrix_kernel<T><<<ceil_div(s * n, 256), 256, 0, st>>>(s, n, W, ldw, prec);
+            launch<RoundMatrix<T>>(ex, ceil_div(s * n, 256), 1, RoundMatrixArgs{s, n, W, ldw, prec});
     }
+    ex.stage(ST_QR);
     for (int64_t c0 = 0; c0 < n; c0 += NBv) {
+        ex.iter((uint32_t)(c0 / NBv));
         const int w = (int)((n - c0 < NBv) ? n - c0 : NBv);
         const int64_t h = s - c0;
         T* Wp = W + c0 + c0 * ldw;
-        if (NBv == 16) panel_dispatch<T, 16>(h, w, Wp, ldw, V, s, Tm, st);
-        else panel_dispatch<T, 8>(h, w, Wp, ldw, V, s, Tm, st);
+        if (NBv == 16) panel_dispatch<T, 16>(ex, h, w, Wp, ldw, V, s, Tm);
+        else panel_dispatch<T, 8>(ex, h, w, Wp, ldw, V, s, Tm);
         const int64_t rem = n - c0 - w;
         if (rem <= 0) break;
         T* Wt = W + c0 + (c0 + w) * ldw;
-        // P[z] = (W_trail^T V) over row chunks  (rem x w)
+        // P[z] = (W_trail^T V) over row chunks  (rem x w); at most
+        // qr_max_splits(s) chunks (the partial buffer is sized for that)
         GemmArgs g{};
         g.M = rem; g.N = w; g.K = h;
         g.A = Wt; g.lda = ldw; g.transA = 1;
         g.B = V; g.ldb = s; g.transB = 0;
         int64_t splits, kc;
-        plan_splitk(h, ceil_div(rem, 128), &splits, &kc);
+        plan_splitk(h, ceil_div(rem, 128), &splits, &kc, ex.kchunk_fixed ? 512 : 0);
         g.splits = splits; g.kchunk = kc;
         g.P = P;
-        if constexpr (sizeof(T) == 8) gemm_f64_partials(g, st);
-        else gemm_f32_partials(g, st);
-        if (NBv == 16) qr_tz_kernel<T, 16><<<ceil_div(rem, 16), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
-        else qr_tz_kernel<T, 8><<<ceil_div(rem, 16), 256, 0, st>>>(rem, w, P, splits, Tm, Z);
+        if constexpr (sizeof(T) == 8) gemm_f64_partials(ex, g);
+        else gemm_f32_partials(ex, g);
+        const QrTzArgs ta{rem, w, P, splits, Tm, Z};
+        if (NBv == 16) launch<QrTz<T, 16>>(ex, ceil_div(rem, 16), 1, ta);
+        else launch<QrTz<T, 8>>(ex, ceil_div(rem, 16), 1, ta);
         // W_trail -= V Z
         GemmArgs u{};
         u.M = h; u.N = rem; u.K = w;
@@ -397,19 +481,20 @@ static int qr_run(int64_t s, int64_t n, T* W, int64_t ldw, int prec, double* R, 
         u.alpha = -1.0; u.beta = 1.0;
         u.Cin = Wt; u.ldcin = ldw; u.C = Wt; u.ldc = ldw;
         u.splits = 1;
-        if constexpr (sizeof(T) == 8) gemm_f64(u, st);
-        else gemm_f32(u, st);
+        if constexpr (sizeof(T) == 8) gemm_f64(ex, u);
+        else gemm_f32(ex, u);
     }
-    extract_r_kernel<T><<<ceil_div(n * n, 256), 256, 0, st>>>(n, W, ldw, prec, R, ldr);
-    r_diag_check_kernel<<<1, 1024, 0, st>>>(n, R, ldr, info);
-    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+    ex.stage(ST_QR_EXTRACT);
+    launch<ExtractR<T>>(ex, ceil_div(n * n, 256), 1, ExtractRArgs{n, W, ldw, prec, R, ldr});
+    launch<RDiagCheck>(ex, 1, 1, RDiagCheck::Args{n, R, ldr, info});
+    return launch_status(ex);
 }
 
-int qr_r(int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr, int32_t* info,
-         void* work, size_t work_bytes, hipStream_t st)
+int qr_r(Exec& ex, int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr,
+         int32_t* info, void* work, size_t work_bytes)
 {
-    if (prec == PNE_PREC_FP64) return qr_run<double>(s, n, (double*)W, ldw, prec, R, ldr, info, work, work_bytes, st);
-    return qr_run<float>(s, n, (float*)W, ldw, prec, R, ldr, info, work, work_bytes, st);
+    if (prec == PNE_PREC_FP64) return qr_run<double>(ex, s, n, (double*)W, ldw, prec, R, ldr, info, work, work_bytes);
+    return qr_run<float>(ex, s, n, (float*)W, ldw, prec, R, ldr, info, work, work_bytes);
 }
 
 }  // namespace pne

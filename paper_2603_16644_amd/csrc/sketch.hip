@@ -19,6 +19,7 @@
 #include "common.h"
 #include "convert.h"
 #include "kernels.h"
+#include "launch.h"
 #include "philox.h"
 #include "profile.h"
 
@@ -70,14 +71,28 @@ __device__ __forceinline__ typename Op<OP>::T to_op(float x)
 // ---------------------------------------------------------------- 1. Omega
 // out[i * ldk + k] = Omega(i, k0 + k) in the operand format, i < s, k < kc;
 // zero for kc <= k < ldk.
+struct OmegaArgs {
+    uint64_t seed;
+    uint32_t pid;
+    int64_t s, k0, kc, ldk;
+    void* out;
+};
 template <int OP>
-__global__ __launch_bounds__(256) void omega_gen_kernel(uint64_t seed, uint32_t pid, int64_t s,
-                                                        int64_t k0, int64_t kc, int64_t ldk,
-                                                        typename Op<OP>::T* __restrict__ out)
+struct OmegaGen {
+    typedef OmegaArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const OmegaArgs& a, int bx, int by);
+};
+template <int OP>
+__device__ void OmegaGen<OP>::run(const OmegaArgs& a, int bx, int by)
 {
     typedef typename Op<OP>::T T;
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t q = blockIdx.y;
+    const uint64_t seed = a.seed;
+    const uint32_t pid = a.pid;
+    const int64_t s = a.s, k0 = a.k0, kc = a.kc, ldk = a.ldk;
+    T* __restrict__ out = (T*)a.out;
+    const int64_t k = (int64_t)bx * 256 + threadIdx.x;
+    const int64_t q = by;
     if (k >= ldk) return;
     T v[4];
     if (k < kc) {
@@ -97,29 +112,47 @@ __global__ __launch_bounds__(256) void omega_gen_kernel(uint64_t seed, uint32_t 
 
 // ---------------------------------------------------------------- 2. quantize A
 // Unscaled formats: Aq[j * ldk + k] = op(A(k0 + k, j)); zero padding.
+struct QuantArgs {
+    const double* A;
+    int64_t lda, k0, kc, ldk, br, n;
+    void* Aq;
+    float* sc;
+};
 template <int OP>
-__global__ __launch_bounds__(256) void quantize_plain_kernel(const double* __restrict__ A,
-                                                             int64_t lda, int64_t k0, int64_t kc,
-                                                             int64_t ldk,
-                                                             typename Op<OP>::T* __restrict__ Aq)
+struct QuantizePlain {
+    typedef QuantArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const QuantArgs& a, int bx, int by);
+};
+template <int OP>
+__device__ void QuantizePlain<OP>::run(const QuantArgs& a, int bx, int by)
 {
-    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t j = blockIdx.y;
+    const double* __restrict__ A = a.A;
+    const int64_t lda = a.lda, k0 = a.k0, kc = a.kc, ldk = a.ldk;
+    typename Op<OP>::T* __restrict__ Aq = (typename Op<OP>::T*)a.Aq;
+    const int64_t k = (int64_t)bx * 256 + threadIdx.x;
+    const int64_t j = by;
     if (k >= ldk) return;
-    float a = (k < kc) ? (float)A[(k0 + k) + j * lda] : 0.0f;
-    Aq[j * ldk + k] = to_op<OP>(a);
+    const float v = (k < kc) ? (float)A[(k0 + k) + j * lda] : 0.0f;
+    Aq[j * ldk + k] = to_op<OP>(v);
 }
 
 // Block-scaled formats: one work-group per (block of `br` rows, column j).
 template <int OP>
-__global__ __launch_bounds__(256) void quantize_scaled_kernel(const double* __restrict__ A,
-                                                              int64_t lda, int64_t k0, int64_t kc,
-                                                              int64_t ldk, int64_t br, int64_t n,
-                                                              typename Op<OP>::T* __restrict__ Aq,
-                                                              float* __restrict__ sc)
+struct QuantizeScaled {
+    typedef QuantArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const QuantArgs& a, int bx, int by);
+};
+template <int OP>
+__device__ void QuantizeScaled<OP>::run(const QuantArgs& a, int bx, int by)
 {
+    const double* __restrict__ A = a.A;
+    const int64_t lda = a.lda, k0 = a.k0, kc = a.kc, ldk = a.ldk, br = a.br, n = a.n;
+    typename Op<OP>::T* __restrict__ Aq = (typename Op<OP>::T*)a.Aq;
+    float* __restrict__ sc = a.sc;
     __shared__ float red[4];
-    const int64_t kb = blockIdx.x, j = blockIdx.y;
+    const int64_t kb = bx, j = by;
     const int64_t r0 = kb * br;
     float amax = 0.0f;
     for (int64_t r = r0 + threadIdx.x; r < r0 + br && r < kc; r += 256)
@@ -172,15 +205,32 @@ __device__ __forceinline__ v4f mfma16(const typename Op<OP>::T* a, const typenam
     }
 }
 
+struct GemmLpArgs {
+    const void* Om;
+    const void* Aq;
+    int64_t ldk, M, N;
+    const float* sc;
+    int64_t br;
+    float* P;
+    int64_t kchunk;
+    int accumulate;
+};
 template <int OP, bool SCALED>
-__global__ __launch_bounds__(256) void gemm_lp_kernel(const typename Op<OP>::T* __restrict__ Om,
-                                                      const typename Op<OP>::T* __restrict__ Aq,
-                                                      int64_t ldk, int64_t M, int64_t N,
-                                                      const float* __restrict__ sc, int64_t br,
-                                                      float* __restrict__ P, int64_t kchunk,
-                                                      int accumulate)
+struct GemmLp {
+    typedef GemmLpArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const GemmLpArgs& a, int bx, int by);
+};
+template <int OP, bool SCALED>
+__device__ void GemmLp<OP, SCALED>::run(const GemmLpArgs& a, int bx, int by)
 {
     typedef typename Op<OP>::T T;
+    const T* __restrict__ Om = (const T*)a.Om;
+    const T* __restrict__ Aq = (const T*)a.Aq;
+    const int64_t ldk = a.ldk, M = a.M, N = a.N, br = a.br, kchunk = a.kchunk;
+    const float* __restrict__ sc = a.sc;
+    float* __restrict__ P = a.P;
+    const int accumulate = a.accumulate;
     constexpr int E = sizeof(T);
     constexpr int PADE = 16 / E;                 // 16 bytes of padding per LDS row
     constexpr int LDR = LP_BK + PADE;            // LDS row length in elements
@@ -192,9 +242,9 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const typename Op<OP>::T* 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w & 1, wn = w >> 1;
     const int64_t tiles_m = (M + LP_BM - 1) / LP_BM;
-    const int64_t i0 = (int64_t)(blockIdx.x % tiles_m) * LP_BM;
-    const int64_t j0 = (int64_t)(blockIdx.x / tiles_m) * LP_BN;
-    const int64_t kbeg = (int64_t)blockIdx.y * kchunk;
+    const int64_t i0 = (int64_t)(bx % tiles_m) * LP_BM;
+    const int64_t j0 = (int64_t)(bx / tiles_m) * LP_BN;
+    const int64_t kbeg = (int64_t)by * kchunk;
     const int64_t kend = (kbeg + kchunk < ldk) ? kbeg + kchunk : ldk;
 
     v4f acc[4][4], tmp[4][4];
@@ -274,7 +324,7 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const typename Op<OP>::T* 
             }
         }
     }
-    float* Pp = P + (int64_t)blockIdx.y * M * N;
+    float* Pp = P + (int64_t)by * M * N;
 #pragma unroll
     for (int ti = 0; ti < 4; ++ti) {
         const int64_t i = i0 + wm * 64 + ti * 16 + r16;
@@ -295,13 +345,30 @@ __global__ __launch_bounds__(256) void gemm_lp_kernel(const typename Op<OP>::T* 
 
 // ---------------------------------------------------------------- 4. reduction
 // As = scale * sum_split P[split]  (fixed order), written as FP32 and/or FP64.
+struct SketchReduceArgs {
+    const void* P;
+    int64_t splits, M, N;
+    double scale;
+    float* o32;
+    int64_t ld32;
+    double* o64;
+    int64_t ld64;
+};
 template <typename TP>
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const TP* __restrict__ P, int64_t splits,
-                                                            int64_t M, int64_t N, double scale,
-                                                            float* __restrict__ o32, int64_t ld32,
-                                                            double* __restrict__ o64, int64_t ld64)
+struct SketchReduce {
+    typedef SketchReduceArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const SketchReduceArgs& a, int bx, int by);
+};
+template <typename TP>
+__device__ void SketchReduce<TP>::run(const SketchReduceArgs& a, int bx, int)
 {
-    const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const TP* __restrict__ P = (const TP*)a.P;
+    const int64_t splits = a.splits, M = a.M, N = a.N, ld32 = a.ld32, ld64 = a.ld64;
+    const double scale = a.scale;
+    float* __restrict__ o32 = a.o32;
+    double* __restrict__ o64 = a.o64;
+    const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     if (idx >= M * N) return;
     const int64_t i = idx % M, j = idx / M;
     TP s = 0;
@@ -311,13 +378,13 @@ __global__ __launch_bounds__(256) void sketch_reduce_kernel(const TP* __restrict
 }
 
 // ---------------------------------------------------------------- host driver
-size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
+size_t sketch_workspace_bytes(int64_t m, int64_t n, int64_t s, int prec, int64_t br, int64_t kchunk_fixed)
 {
-    SketchPlan p = plan_sketch(m, n, s, prec, br);
+    SketchPlan p = plan_sketch(m, n, s, prec, br, kchunk_fixed);
     return p.bytes;
 }
 
-SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
+SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br, int64_t kchunk_fixed)
 {
     SketchPlan p{};
     const int op = prec_to_opk(prec);
@@ -331,16 +398,24 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
     p.chunk = mpad < max_chunk ? mpad : max_chunk;
     p.nchunks = ceil_div(m, p.chunk);
     p.ldk = p.chunk;  // multiple of 64
-    // split-K so that tiles x splits fills the machine
-    int64_t tiles = ceil_div(s, LP_BM) * ceil_div(n, LP_BN);
-    if (op == OPK_F64) tiles = ceil_div(s, 128) * ceil_div(n, 128);
-    int64_t want = ceil_div(1024, tiles);
-    int64_t maxsplit = p.ldk / (4 * align);
-    if (maxsplit < 1) maxsplit = 1;
-    p.splits = want < maxsplit ? want : maxsplit;
-    if (p.splits < 1) p.splits = 1;
-    p.kchunk = ceil_div(ceil_div(p.ldk, p.splits), align) * align;
-    p.splits = ceil_div(p.ldk, p.kchunk);
+    if (kchunk_fixed > 0) {
+        // batches: K chunks of a fixed length (a multiple of the alignment)
+        int64_t kc = ceil_div(kchunk_fixed, align) * align;
+        if (kc > p.ldk) kc = p.ldk;
+        p.kchunk = kc;
+        p.splits = ceil_div(p.ldk, kc);
+    } else {
+        // split-K so that tiles x splits fills the machine
+        int64_t tiles = ceil_div(s, LP_BM) * ceil_div(n, LP_BN);
+        if (op == OPK_F64) tiles = ceil_div(s, 128) * ceil_div(n, 128);
+        int64_t want = ceil_div(1024, tiles);
+        int64_t maxsplit = p.ldk / (4 * align);
+        if (maxsplit < 1) maxsplit = 1;
+        p.splits = want < maxsplit ? want : maxsplit;
+        if (p.splits < 1) p.splits = 1;
+        p.kchunk = ceil_div(ceil_div(p.ldk, p.splits), align) * align;
+        p.splits = ceil_div(p.ldk, p.kchunk);
+    }
     p.op = op;
     Arena ar(nullptr, 0);
     ar.take<char>((size_t)s * p.ldk * E);                           // Omega_q
@@ -352,14 +427,13 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br)
 }
 
 template <int OP>
-static void launch_chunk(const SketchPlan& p, const double* A, int64_t lda, int64_t k0, int64_t kc,
-                         int64_t n, int64_t s, uint64_t seed, uint32_t pid, int64_t br, void* Omq,
-                         void* Aq, float* sc, void* P, int accumulate, hipStream_t st)
+static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t lda, int64_t k0,
+                         int64_t kc, int64_t n, int64_t s, uint64_t seed, uint32_t pid, int64_t br,
+                         void* Omq, void* Aq, float* sc, void* P, int accumulate)
 {
-    typedef typename Op<OP>::T T;
-    dim3 gg(ceil_div(p.ldk, 256), ceil_div(s, 4));
-    omega_gen_kernel<OP><<<gg, 256, 0, st>>>(seed, pid, s, k0, kc, p.ldk, (T*)Omq);
-    prof_mark(PH_SK_OMEGA, st);
+    launch<OmegaGen<OP>>(ex, ceil_div(p.ldk, 256), ceil_div(s, 4),
+                         OmegaArgs{seed, pid, s, k0, kc, p.ldk, Omq});
+    if (!ex.recording()) prof_mark(PH_SK_OMEGA, ex.st);
     if constexpr (OP == OPK_F64) {
         // C(s x n) = Omega_q (rows contiguous over k) * A(chunk rows)
         GemmArgs g{};
@@ -368,31 +442,27 @@ static void launch_chunk(const SketchPlan& p, const double* A, int64_t lda, int6
         g.B = A + k0; g.ldb = lda; g.transB = 0;
         g.splits = p.splits; g.kchunk = p.kchunk;
         g.P = (double*)P; g.accumulate_partials = accumulate;
-        gemm_f64_partials(g, st);
+        gemm_f64_partials(ex, g);
     } else {
         constexpr bool SC = (OP == OPK_FP8 || OP == OPK_F16);
-        if constexpr (SC) {
-            dim3 gq(ceil_div(p.ldk, br), n);
-            quantize_scaled_kernel<OP><<<gq, 256, 0, st>>>(A, lda, k0, kc, p.ldk, br, n, (T*)Aq, sc);
-        } else {
-            dim3 gq(ceil_div(p.ldk, 256), n);
-            quantize_plain_kernel<OP><<<gq, 256, 0, st>>>(A, lda, k0, kc, p.ldk, (T*)Aq);
-        }
-        prof_mark(PH_SK_QUANT, st);
-        dim3 gm(ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits);
-        gemm_lp_kernel<OP, SC><<<gm, 256, 0, st>>>((const T*)Omq, (const T*)Aq, p.ldk, s, n, sc, br,
-                                                   (float*)P, p.kchunk, accumulate);
+        const QuantArgs q{A, lda, k0, kc, p.ldk, br, n, Aq, sc};
+        if constexpr (SC) launch<QuantizeScaled<OP>>(ex, ceil_div(p.ldk, br), n, q);
+        else launch<QuantizePlain<OP>>(ex, ceil_div(p.ldk, 256), n, q);
+        if (!ex.recording()) prof_mark(PH_SK_QUANT, ex.st);
+        launch<GemmLp<OP, SC>>(ex, ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits,
+                               GemmLpArgs{Omq, Aq, p.ldk, s, n, sc, br, (float*)P, p.kchunk, accumulate});
     }
-    prof_mark(PH_SK_GEMM, st);
+    if (!ex.recording()) prof_mark(PH_SK_GEMM, ex.st);
 }
 
 // A_s = Omega A in precision `prec`; writes As32 (ld32) and/or As64 (ld64).
-int sketch_run(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+int sketch_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
                uint32_t pid, int prec, int64_t br, float* As32, int64_t ld32, double* As64,
-               int64_t ld64, void* work, size_t work_bytes, hipStream_t st)
+               int64_t ld64, void* work, size_t work_bytes)
 {
-    SketchPlan p = plan_sketch(m, n, s, prec, br);
+    SketchPlan p = plan_sketch(m, n, s, prec, br, ex.kchunk_fixed);
     if (work_bytes < p.bytes) return PNE_EWORKSPACE;
+    ex.stage(ST_SKETCH);
     const int64_t E = opk_bytes(p.op);
     Arena ar(work, work_bytes);
     void* Omq = ar.take<char>((size_t)s * p.ldk * E);
@@ -404,24 +474,22 @@ int sketch_run(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, ui
         const int64_t k0 = c * p.chunk;
         const int64_t kc = (m - k0 < p.chunk) ? m - k0 : p.chunk;
         const int acc = c > 0;
+        ex.iter((uint32_t)c);
         switch (p.op) {
-        case OPK_F64: launch_chunk<OPK_F64>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
-        case OPK_F32: launch_chunk<OPK_F32>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
-        case OPK_BF16: launch_chunk<OPK_BF16>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
-        case OPK_F16: launch_chunk<OPK_F16>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
-        case OPK_FP8: launch_chunk<OPK_FP8>(p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc, st); break;
+        case OPK_F64: launch_chunk<OPK_F64>(ex, p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc); break;
+        case OPK_F32: launch_chunk<OPK_F32>(ex, p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc); break;
+        case OPK_BF16: launch_chunk<OPK_BF16>(ex, p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc); break;
+        case OPK_F16: launch_chunk<OPK_F16>(ex, p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc); break;
+        case OPK_FP8: launch_chunk<OPK_FP8>(ex, p, A, lda, k0, kc, n, s, seed, pid, br, Omq, Aq, sc, P, acc); break;
         }
     }
+    ex.stage(ST_SKETCH_REDUCE);
     const double scale = 1.0 / sqrt((double)s);
-    dim3 gr(ceil_div(s * n, 256));
-    if (p.op == OPK_F64)
-        sketch_reduce_kernel<double><<<gr, 256, 0, st>>>((const double*)P, p.splits, s, n, scale,
-                                                         As32, ld32, As64, ld64);
-    else
-        sketch_reduce_kernel<float><<<gr, 256, 0, st>>>((const float*)P, p.splits, s, n, scale, As32,
-                                                        ld32, As64, ld64);
-    prof_mark(PH_SK_REDUCE, st);
-    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
+    const SketchReduceArgs ra{P, p.splits, s, n, scale, As32, ld32, As64, ld64};
+    if (p.op == OPK_F64) launch<SketchReduce<double>>(ex, ceil_div(s * n, 256), 1, ra);
+    else launch<SketchReduce<float>>(ex, ceil_div(s * n, 256), 1, ra);
+    if (!ex.recording()) prof_mark(PH_SK_REDUCE, ex.st);
+    return launch_status(ex);
 }
 
 }  // namespace pne

@@ -9,18 +9,35 @@
 // Cholesky panel (X L^T = C, TRANS_LOWER).
 #include "common.h"
 #include "kernels.h"
+#include "launch.h"
 
 namespace pne {
 
 constexpr int LEAF = 64;
 
-template <typename T, bool TRANS_LOWER, bool UNIT, int NTH>
-__global__ __launch_bounds__(NTH) void trsm_leaf_kernel(int64_t m, int w, T* __restrict__ X,
-                                                        int64_t rs, int64_t cs,
-                                                        const T* __restrict__ Rb, int64_t ldr)
+struct TrsmLeafArgs {
+    int64_t m;
+    int w;
+    void* X;
+    int64_t rs, cs;
+    const void* Rb;
+    int64_t ldr;
+};
+template <typename T, bool TRANS_LOWER, bool UNIT, int NT>
+struct TrsmLeaf {
+    typedef TrsmLeafArgs Args;
+    static constexpr int NTH = NT, WPE = 0;
+    static __device__ void run(const TrsmLeafArgs& a, int bx, int by);
+};
+template <typename T, bool TRANS_LOWER, bool UNIT, int NT>
+__device__ void TrsmLeaf<T, TRANS_LOWER, UNIT, NT>::run(const TrsmLeafArgs& a, int bx, int)
 {
+    const int64_t m = a.m, rs = a.rs, cs = a.cs, ldr = a.ldr;
+    const int w = a.w;
+    T* __restrict__ X = (T*)a.X;
+    const T* __restrict__ Rb = (const T*)a.Rb;
     __shared__ T Rs[LEAF * LEAF];  // Rs[c * 64 + k] = R(k, c), k <= c
-    for (int e = threadIdx.x; e < LEAF * LEAF; e += NTH) {
+    for (int e = threadIdx.x; e < LEAF * LEAF; e += NT) {
         const int c = e / LEAF, k = e % LEAF;
         T v = 0;
         if (c < w && k <= c) v = TRANS_LOWER ? Rb[c + (int64_t)k * ldr] : Rb[k + (int64_t)c * ldr];
@@ -28,7 +45,7 @@ __global__ __launch_bounds__(NTH) void trsm_leaf_kernel(int64_t m, int w, T* __r
         Rs[e] = v;
     }
     __syncthreads();
-    const int64_t i = (int64_t)blockIdx.x * NTH + threadIdx.x;
+    const int64_t i = (int64_t)bx * NT + threadIdx.x;
     if (i >= m) return;
     T x[LEAF];
 #pragma unroll
@@ -49,26 +66,28 @@ __global__ __launch_bounds__(NTH) void trsm_leaf_kernel(int64_t m, int w, T* __r
 }
 
 template <typename T, bool TL, bool UNIT>
-void trsm_leaf(int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr, hipStream_t st)
+void trsm_leaf(Exec& ex, int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr)
 {
     if (m <= 0) return;
+    const TrsmLeafArgs a{m, w, X, rs, cs, Rb, ldr};
     // short panels (factorizations) use one wavefront per work-group to
     // spread over more compute units
-    if (m < 16384) trsm_leaf_kernel<T, TL, UNIT, 64><<<ceil_div(m, 64), 64, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
-    else trsm_leaf_kernel<T, TL, UNIT, 256><<<ceil_div(m, 256), 256, 0, st>>>(m, w, X, rs, cs, Rb, ldr);
+    if (m < 16384) launch<TrsmLeaf<T, TL, UNIT, 64>>(ex, ceil_div(m, 64), 1, a);
+    else launch<TrsmLeaf<T, TL, UNIT, 256>>(ex, ceil_div(m, 256), 1, a);
 }
-template void trsm_leaf<double, true, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
-template void trsm_leaf<float, true, false>(int64_t, int, float*, int64_t, int64_t, const float*, int64_t, hipStream_t);
-template void trsm_leaf<double, true, true>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
-template void trsm_leaf<double, false, false>(int64_t, int, double*, int64_t, int64_t, const double*, int64_t, hipStream_t);
+template void trsm_leaf<double, true, false>(Exec&, int64_t, int, double*, int64_t, int64_t, const double*, int64_t);
+template void trsm_leaf<float, true, false>(Exec&, int64_t, int, float*, int64_t, int64_t, const float*, int64_t);
+template void trsm_leaf<double, true, true>(Exec&, int64_t, int, double*, int64_t, int64_t, const double*, int64_t);
+template void trsm_leaf<double, false, false>(Exec&, int64_t, int, double*, int64_t, int64_t, const double*, int64_t);
 
 // Column blocks of 128: one GEMM brings the block up to date with every
 // earlier column, then the two 64-column halves are finished by the leaf with
 // a 64-deep GEMM in between.
-void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
-                      int64_t ldr, double* Ap, int64_t ldap, hipStream_t st)
+void trsm_right_upper(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* R,
+                      int64_t ldr, double* Ap, int64_t ldap)
 {
     for (int64_t c0 = 0; c0 < n; c0 += 2 * LEAF) {
+        ex.iter((uint32_t)(c0 / (2 * LEAF)));
         const int w = (int)((n - c0 < 2 * LEAF) ? n - c0 : 2 * LEAF);
         GemmArgs g{};
         g.M = m; g.N = w; g.K = c0;
@@ -78,9 +97,9 @@ void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const 
         g.Cin = A + c0 * lda; g.ldcin = lda;
         g.C = Ap + c0 * ldap; g.ldc = ldap;
         g.splits = 1;
-        gemm_f64(g, st);
+        gemm_f64(ex, g);
         const int w1 = w < LEAF ? w : LEAF;
-        trsm_leaf<double, false, false>(m, w1, Ap + c0 * ldap, 1, ldap, R + c0 + c0 * ldr, ldr, st);
+        trsm_leaf<double, false, false>(ex, m, w1, Ap + c0 * ldap, 1, ldap, R + c0 + c0 * ldr, ldr);
         if (w > LEAF) {
             const int64_t c1 = c0 + LEAF;
             GemmArgs h{};
@@ -91,8 +110,8 @@ void trsm_right_upper(int64_t m, int64_t n, const double* A, int64_t lda, const 
             h.Cin = Ap + c1 * ldap; h.ldcin = ldap;
             h.C = Ap + c1 * ldap; h.ldc = ldap;
             h.splits = 1;
-            gemm_f64(h, st);
-            trsm_leaf<double, false, false>(m, w - LEAF, Ap + c1 * ldap, 1, ldap, R + c1 + c1 * ldr, ldr, st);
+            gemm_f64(ex, h);
+            trsm_leaf<double, false, false>(ex, m, w - LEAF, Ap + c1 * ldap, 1, ldap, R + c1 + c1 * ldr, ldr);
         }
     }
 }

@@ -71,3 +71,30 @@ def test_workspace_grows_with_problem(pne):
     a = L.pne_workspace_size(10_000, 100, ctypes.byref(o), 0)
     b = L.pne_workspace_size(100_000, 100, ctypes.byref(o), 0)
     assert b > a >= 10_000 * 100 * 8   # at least A_p
+
+
+def test_batched_workspace_sizing_runs_on_host(pne):
+    """The batched workspace query records the whole launch sequence of every
+    member on the host (no device call) and bounds its group tables."""
+    from paper_2603_16644_amd._lib import ProblemDesc
+    L = pne.lib()
+    shapes = [(2000, 64), (3100, 100), (2500, 33)]
+    arr = (ProblemDesc * 3)()
+    ao = bo = xo = 0
+    for i, (m, n) in enumerate(shapes):
+        arr[i] = ProblemDesc(m, n, m, ao, bo, xo)
+        ao += m * n
+        bo += m
+        xo += n
+    o = pne.make_opts(sketch_prec="bf16", qr_prec="fp32")
+    p = ctypes.cast(arr, ctypes.c_void_p)
+    total = L.pne_batched_workspace_size(3, p, ctypes.byref(o), 0)
+    singles = sum(L.pne_workspace_size(m, n, ctypes.byref(o), 0) for m, n in shapes)
+    assert total > 0 and total >= 0.5 * singles
+    assert L.pne_batched_workspace_size(3, p, ctypes.byref(o), 1) > 0     # HPNE
+    auto = pne.make_opts()
+    assert L.pne_batched_workspace_size(3, p, ctypes.byref(auto), 0) > total
+    arr[1] = ProblemDesc(50, 100, 50, 0, 0, 0)                           # m < n
+    assert L.pne_batched_workspace_size(3, p, ctypes.byref(o), 0) == 0
+    one = ctypes.c_void_p(256)
+    assert L.pne_solve_batched(3, p, one, one, one, ctypes.byref(o), 0, one, 1 << 30, one, None) == -1

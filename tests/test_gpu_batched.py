@@ -1,0 +1,146 @@
+"""GPU checks of the batched solver (pne_solve_batched): many independent
+problems of uneven m, n and kappa solved by grouped launches, one per step of
+the pipeline.  Each member is checked against its known solution and the
+CPU oracle's QR solve, and against the single-problem solver."""
+import numpy as np
+import pytest
+import torch
+
+from workloads import make_problem
+from workloads.problems import draw_batch_shapes
+
+pytestmark = pytest.mark.gpu
+U64 = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def pne():
+    import paper_2603_16644_amd as p
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    p.lib()
+    return p
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().cpu().numpy()
+
+
+def relerr(x, y):
+    return float(np.linalg.norm(np.asarray(x) - np.asarray(y)) / np.linalg.norm(y))
+
+
+def pack(probs, device="cuda"):
+    """Concatenate the members' A (column-major), b and x slots."""
+    descs, ao, bo, xo = [], 0, 0, 0
+    for p in probs:
+        descs.append(dict(m=p.m, n=p.n, lda=p.m, a_offset=ao, b_offset=bo, x_offset=xo))
+        ao += p.m * p.n
+        bo += p.m
+        xo += p.n
+    A = torch.empty(ao, dtype=torch.float64, device=device)
+    b = torch.empty(bo, dtype=torch.float64, device=device)
+    for p, d in zip(probs, descs):
+        # At (n, m) row-major is A column-major
+        A[d["a_offset"]:d["a_offset"] + p.m * p.n] = p.At.reshape(-1).to(device)
+        b[d["b_offset"]:d["b_offset"] + p.m] = p.b.to(device)
+    x = torch.zeros(xo, dtype=torch.float64, device=device)
+    return A, b, x, descs
+
+
+SHAPES = [(2000, 64, 1e3, 1e-4), (3100, 100, 1e5, 1e-8), (2500, 33, 1e2, 1e-2), (6000, 300, 1e6, 1e-6),
+          (1999, 96, 1e4, 1e-3), (4097, 129, 1e7, 1e-10)]
+
+
+@pytest.fixture(scope="module")
+def small_batch(orc):
+    probs = [make_problem(m, n, k, r, seed=40000 + i) for i, (m, n, k, r) in enumerate(SHAPES)]
+    err_qr = [relerr(orc.qr_ls(p.numpy_A(), p.numpy_b()), p.numpy_x_star()) for p in probs]
+    return probs, err_qr
+
+
+@pytest.mark.parametrize("hpne", [False, True])
+def test_batched_members_accurate_and_match_single(pne, small_batch, hpne):
+    probs, err_qr = small_batch
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=5, sketch_prec="bf16", qr_prec="fp32", refine_steps=3)
+    info = pne.pne_solve_batched(A, b, x, descs, opts=o, hpne=hpne)
+    assert np.all(host(info) == 0)
+    xb = host(x)
+    fn = pne.hpne_solve if hpne else pne.pne_solve
+    for i, (p, d) in enumerate(zip(probs, descs)):
+        xi = xb[d["x_offset"]:d["x_offset"] + p.n]
+        xs = p.numpy_x_star()
+        assert relerr(xi, xs) <= 10 * err_qr[i], (i, relerr(xi, xs), err_qr[i])
+        oi = pne.make_opts(seed=5, problem_id=i, sketch_prec="bf16", qr_prec="fp32", refine_steps=3)
+        x1, _, _ = fn(p.A.cuda(), p.b.cuda(), opts=oi)
+        assert relerr(xi, host(x1)) <= 10 * err_qr[i] + relerr(host(x1), xs)
+
+
+def test_batched_deterministic(pne, small_batch):
+    probs, _ = small_batch
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=9, sketch_prec="fp16", qr_prec="fp16", refine_steps=2)
+    pne.pne_solve_batched(A, b, x, descs, opts=o)
+    x0 = host(x).copy()
+    x.zero_()
+    pne.pne_solve_batched(A, b, x, descs, opts=o)
+    assert np.array_equal(x0, host(x))
+
+
+def test_batched_auto_mixes_precisions(pne, orc):
+    """AUTO picks per member (kappa 1e2 -> half, 3e3 -> single, 1e10 -> double);
+    members of different precisions run in the same batched call."""
+    shapes = [(3000, 100, 1e2, 1e-6), (3000, 100, 3e3, 1e-6), (3000, 100, 1e10, 1e-6), (2500, 70, 1e2, 1e-3)]
+    probs = [make_problem(m, n, k, r, seed=41000 + i) for i, (m, n, k, r) in enumerate(shapes)]
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=3, sketch_prec="auto", qr_prec="auto", refine_steps=2)
+    info = pne.pne_solve_batched(A, b, x, descs, opts=o)
+    assert np.all(host(info) == 0)
+    xb = host(x)
+    picks = []
+    for i, (p, d) in enumerate(zip(probs, descs)):
+        xi = xb[d["x_offset"]:d["x_offset"] + p.n]
+        err_qr = relerr(orc.qr_ls(p.numpy_A(), p.numpy_b()), p.numpy_x_star())
+        assert relerr(xi, p.numpy_x_star()) <= 10 * err_qr
+        picks.append(orc.cond_est(p.numpy_A())[2])
+    assert picks[0] == 3 and picks[2] == 1   # FP16, FP64
+
+
+def test_batched_singular_member_is_isolated(pne):
+    probs = [make_problem(m, n, k, r, seed=42000 + i)
+             for i, (m, n, k, r) in enumerate([(2000, 50, 1e3, 1e-6), (2200, 40, 1e3, 1e-6)])]
+    probs[1].At[7].zero_()          # column 8 of member 1 is zero
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=1, sketch_prec="fp32", qr_prec="fp32", refine_steps=1)
+    info = host(pne.pne_solve_batched(A, b, x, descs, opts=o))
+    assert info[0] == 0 and 1000 < info[1] <= 1000 + 40
+    xb = host(x)
+    assert np.all(np.isfinite(xb[:50])) and np.all(np.isnan(xb[50:90]))
+
+
+# ------------------------------------------------------------------ 512 problems
+
+def test_batch512_known_solutions(pne):
+    """512 problems, m ~ U[2000, 50000], n ~ U[32, 512] with m >= 20 n,
+    kappa log-uniform in [1e2, 1e8], residual log-uniform in [1e-10, 1e-2],
+    BF16 sketches (s = 3n), FP32 QR, three FP64 refinement steps: every member
+    within 10x the first-order least-squares bound kappa u (1 + kappa rho)."""
+    shapes = draw_batch_shapes(512, 0)
+    probs = [make_problem(m, n, k, r, seed=40000 + i, device="cuda") for i, (m, n, k, r) in enumerate(shapes)]
+    A, b, x, descs = pack(probs)
+    xs = [host(p.x_star) for p in probs]
+    for p in probs:
+        p.At = None
+    torch.cuda.empty_cache()
+    o = pne.make_opts(seed=0, sketch_prec="bf16", qr_prec="fp32", refine_steps=3)
+    info = host(pne.pne_solve_batched(A, b, x, descs, opts=o))
+    assert np.all(info == 0), np.nonzero(info)
+    xb = host(x)
+    bad = []
+    for i, (p, d) in enumerate(zip(probs, descs)):
+        e = relerr(xb[d["x_offset"]:d["x_offset"] + p.n], xs[i])
+        bound = p.kappa * U64 * (1 + p.kappa * p.rho)
+        if not e <= 10 * bound:
+            bad.append((i, p.m, p.n, p.kappa, p.rho, e, bound))
+    assert not bad, bad[:10]

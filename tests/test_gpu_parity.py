@@ -196,31 +196,6 @@ def test_known_kappa_skips_estimate(pne):
     assert meta["sketch_prec"] == "fp32" and abs(meta["kappa0"] - 5.0) < 1e-6
 
 
-# ------------------------------------------------------------------ batched
-
-def test_batched_equals_single(pne):
-    shapes = [(2000, 64, 1e3, 1e-4), (3100, 100, 1e5, 1e-8), (2500, 33, 1e2, 1e-2)]
-    probs = [make_problem(m, n, k, r, seed=40000 + i) for i, (m, n, k, r) in enumerate(shapes)]
-    Ablk = np.concatenate([p.numpy_A().ravel(order="F") for p in probs])
-    bblk = np.concatenate([p.numpy_b() for p in probs])
-    descs, ao, bo, xo = [], 0, 0, 0
-    for p in probs:
-        descs.append(dict(m=p.m, n=p.n, lda=p.m, a_offset=ao, b_offset=bo, x_offset=xo))
-        ao += p.m * p.n
-        bo += p.m
-        xo += p.n
-    Ad, bd = torch.from_numpy(Ablk).cuda(), torch.from_numpy(bblk).cuda()
-    xd = torch.zeros(xo, dtype=torch.float64, device="cuda")
-    o = pne.make_opts(seed=5, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
-    info = pne.pne_solve_batched(Ad, bd, xd, descs, opts=o)
-    assert np.all(host(info) == 0)
-    xb = host(xd)
-    for i, (p, d) in enumerate(zip(probs, descs)):
-        oi = pne.make_opts(seed=5, problem_id=i, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
-        x, _, _ = pne.pne_solve(dev(p.numpy_A()), torch.from_numpy(p.numpy_b()).cuda(), opts=oi)
-        assert np.array_equal(host(x), xb[d["x_offset"]:d["x_offset"] + p.n])
-
-
 # ------------------------------------------------------------------ full size (m = 1e5, n = 1e3)
 
 @pytest.fixture(scope="module")
