@@ -44,6 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="mixed path only (profiling runs)")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain elementwise copy (torch.neg) of 512 MiB first, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -103,9 +104,9 @@ def roofline(ph):
     """Dominant single-kernel phase against its MFMA peak (algorithmic flops)."""
     cands = {
         # C = A_p^T A_p (lower triangle incl. diagonal) and c = A_p^T b
-        "gram_gemm": (M * N * (N + 1) + 2 * M * N, PEAK_FP64, "gemm_cm_kernel<double,double,double,128,true>"),
+        "gram_gemm": (M * N * (N + 1) + 2 * M * N, PEAK_FP64, "GemmCm<double,double,double,128,true>"),
         # A_s = Omega A, BF16 operands
-        "sketch_gemm": (2 * S * M * N, PEAK_BF16, "gemm_lp_kernel<bf16,false>"),
+        "sketch_gemm": (2 * S * M * N, PEAK_BF16, "GemmLp<bf16,false>"),
     }
     best = max(cands, key=lambda k: ph.get(k, 0.0))
     flops, peak, kname = cands[best]
@@ -116,7 +117,7 @@ def roofline(ph):
     if os.path.exists(tf):
         try:
             rec = json.load(open(tf)).get(best)
-            if rec and rec.get("source_hash") == source_hash("gemm.hip", "sketch.hip"):
+            if rec and rec.get("source_hash") == source_hash(*rec.get("source_files", ["?"])):
                 traffic = rec["bytes_per_launch"]
         except (ValueError, OSError):
             traffic = None
@@ -125,7 +126,51 @@ def roofline(ph):
             "ms_per_launch": ph[best], "algorithmic_flops": flops}
 
 
-def cpu_baseline(prob, ms_rows=2000):
+def time_batched(pne, steps, warmup):
+    """512 independent problems (m ~ U[2000, 50000], n ~ U[32, 512], m >= 20 n,
+    kappa log-uniform in [1e2, 1e8], residual log-uniform in [1e-10, 1e-2]),
+    BF16 sketches with s = 3n, FP32 QR, one FP64 refinement step, solved by
+    pne_solve_batched (grouped launches).  Returns solves/s and, per member,
+    whether the error is within 10x kappa u (1 + kappa rho)."""
+    import torch
+
+    from workloads import draw_batch_shapes, make_problem, pack_batch
+    shapes = draw_batch_shapes(512, 0)
+    probs = [make_problem(m, n, k, r, seed=40000 + i, device="cuda") for i, (m, n, k, r) in enumerate(shapes)]
+    A, b, x, descs = pack_batch(probs, release=True)
+    xs = [p.x_star for p in probs]
+    torch.cuda.empty_cache()
+    L = pne.lib()
+    out = {"workload": "batch512_m2000-50000_n32-512_k1e2-1e8", "problems": len(probs),
+           "sum_mn": int(sum(p.m * p.n for p in probs))}
+    for refine in (1, 3):
+        o = pne.make_opts(seed=0, sketch_prec="bf16", qr_prec="fp32", refine_steps=refine)
+        for _ in range(warmup):
+            pne.pne_solve_batched(A, b, x, descs, opts=o)
+        torch.cuda.synchronize()
+        L.pne_profile_enable(1)
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = pne.pne_solve_batched(A, b, x, descs, opts=o)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        ms = (ctypes.c_double * 16)()
+        cnt = L.pne_profile_read(ms, 16)
+        L.pne_profile_enable(0)
+        phases = {L.pne_profile_phase_name(i).decode(): round(ms[i], 4) for i in range(cnt) if ms[i] >= 0}
+        ok = 0
+        for p, d, xstar in zip(probs, descs, xs):
+            xi = x[d["x_offset"]:d["x_offset"] + p.n]
+            e = float(torch.linalg.norm(xi - xstar) / torch.linalg.norm(xstar))
+            ok += e <= 10 * p.kappa * U64 * (1 + p.kappa * p.rho)
+        dt = (t1 - t0) / steps
+        out[f"refine{refine}"] = {"solves_per_s": len(probs) / dt, "ms": dt * 1e3,
+                                  "members_within_bound": int(ok), "info_nonzero": int((info != 0).sum()),
+                                  "phases_ms": phases}
+    return out
+
+
+def cpu_baseline(prob, ms_rows=5000):
     """Oracle (plain single-threaded C, FP64 with BF16 operand emulation) timed
     per step on the first `ms_rows` rows of the same A; the row-proportional
     steps are scaled by M / ms_rows, the rest (QR, Cholesky, solves) taken as
@@ -230,6 +275,11 @@ def main():
         line["cpu_baseline"] = cpu_baseline(prob)
     else:
         line["cpu_baseline"] = None
+    if not args.quick and not args.no_batch:
+        print("[bench] timing the 512-problem batch", file=sys.stderr, flush=True)
+        del prob
+        torch.cuda.empty_cache()
+        line["batch512"] = time_batched(pne, max(2, args.steps // 2), 1)
     print(json.dumps(line))
 
 

@@ -56,6 +56,8 @@ struct Buffers {
     double* gv;         // gemv partials
     double* dinv1;      // block inverses: Cholesky factor L, or unit lower L of the LU
     double* dinv2;      // block inverses: R_s (PNE) or U (HPNE)
+    double* Lt;         // PNE: L^T (n x n)
+    double* dinv1t;     // PNE: block inverses of L^T
     float* k0;          // condition estimate
     int32_t* choice;
 };
@@ -106,6 +108,10 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
     b.gv = ar.take<double>(gemv_t_partials(p.m, p.n));
     b.dinv1 = ar.take<double>(dinv_elems(p.n));
     b.dinv2 = ar.take<double>(dinv_elems(p.n));
+    if (!p.hpne) {
+        b.Lt = ar.take<double>((size_t)p.n * p.n);
+        b.dinv1t = ar.take<double>(dinv_elems(p.n));
+    }
     if (own_k0) {
         b.k0 = ar.take<float>(4);
         b.choice = ar.take<int32_t>(4);
@@ -224,19 +230,20 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     mark(ex, PH_GRAM_REDUCE);
     ex.stage(ST_FACTOR);
     if (hpne) lu_factor(ex, n, b.C, n, b.piv, dinfo);
-    else cholesky<double>(ex, n, b.C, n, dinfo);
+    else cholesky<double>(ex, n, b.C, n, dinfo, b.dinv1);
     ex.stage(ST_FACTOR_INV);
     if (hpne) {
         inv_diag_blocks<double>(ex, n, b.C, n, 1, 0, 1, b.dinv1);
         inv_diag_blocks<double>(ex, n, b.C, n, 0, 0, 0, b.dinv2);
     } else {
-        inv_diag_blocks<double>(ex, n, b.C, n, 1, 0, 0, b.dinv1);
         inv_diag_blocks<double>(ex, n, b.R, n, 0, 0, 0, b.dinv2);
+        transpose_f64(ex, n, n, b.C, n, b.Lt, n);
+        transpose_dinv(ex, n, b.dinv1, b.dinv1t);
     }
     mark(ex, PH_FACTOR);
     ex.stage(ST_SOLVE);
     if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx);
-    else pne_solve3(ex, n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.c, dx);
+    else pne_solve3(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx);
     mark(ex, PH_SOLVE);
     ex.stage(ST_REFINE);
     for (int k = 0; k < p.refine; ++k) {
@@ -244,7 +251,7 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
         residual(ex, m, n, dA, lda, db, dx, b.r);
         gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
         if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d);
-        else pne_solve3(ex, n, b.C, n, b.dinv1, b.R, n, b.dinv2, b.y, b.d);
+        else pne_solve3(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d);
         axpy_update(ex, n, dx, b.d);
     }
     ex.stage(ST_FINISH);

@@ -2,8 +2,9 @@
 // Algorithm 1 first step).
 //   G = fl32(A)^T fl32(A)       FP32 MFMA SYRK, split over rows of A
 //   ||G||_1                     max column sum of |G| (symmetric, lower stored)
-//   G = L L^T                   FP32 blocked Cholesky; a bad pivot means the
-//                               estimate "overflows" -> kappa0 = +inf
+//   G = L L^T                   FP32 blocked Cholesky (with the inverses of
+//                               its 64 x 64 diagonal blocks); a bad pivot
+//                               means the estimate "overflows" -> kappa0 = +inf
 //   est ~ ||G^{-1}||_1          Hager's method (Hager 1984): x = (1/n) 1,
 //                               (solves through the inverted 64 x 64
 //                               diagonal blocks of L),
@@ -225,9 +226,7 @@ int condest_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, do
     gemm_ddf(ex, g);
     launch<Norm1Sym>(ex, 1, 1, Norm1Sym::Args{n, G, n, g1});
     ex.stage(ST_CONDEST_FACTOR);
-    cholesky<float>(ex, n, G, n, info);
-    ex.stage(ST_CONDEST_INV);
-    inv_diag_blocks<float>(ex, n, G, n, 1, 0, 0, DL);
+    cholesky<float>(ex, n, G, n, info, DL);
     ex.stage(ST_CONDEST_EST);
     launch<Hager>(ex, 1, 1, Hager::Args{n, G, n, DL, g1, info, dk0, dchoice});
     return launch_status(ex);

@@ -88,8 +88,10 @@ void trsm_right_upper(Exec& ex, int64_t m, int64_t n, const double* A, int64_t l
 template <typename T, bool TL, bool UNIT>
 void trsm_leaf(Exec& ex, int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr);
 // Cholesky (lower, in place) of the n x n matrix C; info word gets 2000+k.
+// Dinv (dinv_elems(n) values) receives the inverses of the 64 x 64 diagonal
+// blocks of L in the layout of inv_diag_blocks.
 template <typename T>
-void cholesky(Exec& ex, int64_t n, T* C, int64_t ldc, int32_t* info);
+void cholesky(Exec& ex, int64_t n, T* C, int64_t ldc, int32_t* info, T* Dinv);
 // LU with partial pivoting in place; piv 0-based; info 3000+k.
 void lu_factor(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, int32_t* info);
 // Householder QR (R only) of the s x n matrix W (in place); R (FP64, n x n,
@@ -100,18 +102,27 @@ int qr_r(Exec& ex, int64_t s, int64_t n, void* W, int64_t ldw, int prec, double*
 bool qr_supported(int64_t s, int prec);
 
 // ---------------------------------------------------------------- vectors
-// inverses of the 64 x 64 diagonal blocks of op(M) (dinv_elems(n) values)
+// inverses of the 64 x 64 diagonal blocks of op(M) (dinv_elems(n) values);
+// blocks block0 .. block0 + nblocks - 1 (nblocks < 0: to the end)
 size_t dinv_elems(int64_t n);
 template <typename T>
-void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv);
+void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv,
+                     int64_t block0 = 0, int64_t nblocks = -1);
 // x = U^{-1} L^{-1} P c (c and x may alias); DL, DU: block inverses of the
 // unit lower L and of U
 void lu_solve2(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
                const double* DU, const double* c, double* x);
 // x = R^{-1} L^{-T} L^{-1} c (PNE: Cholesky factor L, preconditioner R) with
-// the block inverses DL of L and DR of R
-void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* R,
-                int64_t ldr, const double* DR, const double* c, double* x);
+// the block inverses DL of L and DR of R; Lt = L^T stored explicitly (n x n,
+// ld n) with the block inverses DLt of L^T, so that every solve reads its
+// matrix by columns
+void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
+                const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c,
+                double* x);
+// out (c x r, ldo) = in^T (in r x c, ldi)
+void transpose_f64(Exec& ex, int64_t r, int64_t c, const double* in, int64_t ldi, double* out, int64_t ldo);
+// transposes of the 64 x 64 blocks of a block-inverse array (dinv_elems(n))
+void transpose_dinv(Exec& ex, int64_t n, const double* D, double* Dt);
 bool lu_supported(int64_t n);
 // r = b - A x
 void residual(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,

@@ -415,6 +415,7 @@ static void panel_dispatch(Exec& ex, int64_t h, int w, T* Wp, int64_t ldw, T* V,
     if constexpr (sizeof(T) == 4) {
         if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else if (h <= 2048) panel_launch<T, NB, 2, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 2304) panel_launch<T, NB, 3, 768, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else panel_launch<T, NB, 12, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);

@@ -12,69 +12,82 @@ constexpr int TB = 64, TBL = TB + 1;  // diagonal block and its LDS leading dime
 
 // Inverse of every 64 x 64 diagonal block of op(M) (lower or upper; unit
 // diagonal optional): block b goes to Dinv[b*TB*TB + r + c*TB].  One wavefront
-// per block (bx = b); lane c solves op(M)_bb y = e_c column by column.
-// Padding rows and columns beyond n act as the identity.
+// per block (bx = b); lane c solves op(M)_bb y = e_c by substitution in
+// column order (forward for lower, backward for upper) with the block in LDS
+// and the reciprocal diagonal, y in registers (static indices through
+// template recursion).  Padding rows and columns beyond n act as the
+// identity.
+template <typename T, bool UPPER, int K>
+struct InvStep {
+    static __device__ __forceinline__ void run(T (&y)[TB], const T* Ub, const T* rd, T* Ys)
+    {
+        constexpr int k = UPPER ? TB - 1 - K : K;
+        const int lane = threadIdx.x;
+        const T yk = y[k] * rd[k];
+        Ys[k * TBL + lane] = yk;
+#pragma unroll
+        for (int j = 0; j < TB; ++j)
+            if (UPPER ? (j < k) : (j > k)) y[j] -= Ub[j + k * TBL] * yk;
+        __syncthreads();
+        InvStep<T, UPPER, K + 1>::run(y, Ub, rd, Ys);
+    }
+};
+template <typename T, bool UPPER>
+struct InvStep<T, UPPER, TB> {
+    static __device__ __forceinline__ void run(T (&)[TB], const T*, const T*, T*) {}
+};
+
 struct InvDiagArgs {
     int64_t n;
     const void* M;
     int64_t ld;
-    int lower, trans, unit;
+    int trans, unit;
     void* Dinv;
+    int64_t block0;    // first block handled (bx = 0)
 };
-template <typename T>
+template <typename T, bool UPPER>
 struct InvDiag {
     typedef InvDiagArgs Args;
     static constexpr int NTH = 64, WPE = 0;
     static __device__ void run(const InvDiagArgs& a, int bx, int by);
 };
-template <typename T>
-__device__ void InvDiag<T>::run(const InvDiagArgs& a, int bx, int)
+template <typename T, bool UPPER>
+__device__ void InvDiag<T, UPPER>::run(const InvDiagArgs& a, int bx, int)
 {
     const int64_t n = a.n, ld = a.ld;
-    const int lower = a.lower, trans = a.trans, unit = a.unit;
+    const int trans = a.trans, unit = a.unit;
     const T* __restrict__ M = (const T*)a.M;
-    T* __restrict__ Dinv = (T*)a.Dinv;
-    __shared__ T Ub[TB * TBL];
-    const int64_t b0 = (int64_t)bx * TB;
+    const int64_t blk = a.block0 + bx;
+    T* __restrict__ D = (T*)a.Dinv + blk * TB * TB;
+    __shared__ T Ub[TB * TBL];   // Ub[r + c * TBL] = op(M)_bb(r, c)
+    __shared__ T Ys[TB * TBL];   // Ys[r * TBL + c] = inverse(r, c)
+    __shared__ T rd[TB];
+    const int64_t b0 = blk * TB;
     const int bw = (int)((n - b0 < TB) ? n - b0 : TB);
     const int lane = threadIdx.x;
     for (int e = lane; e < TB * TB; e += 64) {
         const int r = e % TB, c = e / TB;
-        const bool in = lower ? (r >= c) : (r <= c);
+        const bool in = UPPER ? (r <= c) : (r >= c);
         T v = 0;
         if (r < bw && c < bw && in) v = trans ? M[(b0 + c) + (b0 + r) * ld] : M[(b0 + r) + (b0 + c) * ld];
         if (r == c && (r >= bw || unit)) v = (T)1;
         Ub[r + c * TBL] = v;
     }
     __syncthreads();
+    rd[lane] = (T)1 / Ub[lane + lane * TBL];
+    __syncthreads();
     T y[TB];
 #pragma unroll
     for (int r = 0; r < TB; ++r) y[r] = (r == lane) ? (T)1 : (T)0;
-    if (lower) {
-#pragma unroll
-        for (int k = 0; k < TB; ++k) {
-            y[k] = y[k] / Ub[k + k * TBL];
-#pragma unroll
-            for (int r = k + 1; r < TB; ++r) y[r] -= Ub[r + k * TBL] * y[k];
-        }
-    } else {
-#pragma unroll
-        for (int k = TB - 1; k >= 0; --k) {
-            y[k] = y[k] / Ub[k + k * TBL];
-#pragma unroll
-            for (int r = 0; r < k; ++r) y[r] -= Ub[r + k * TBL] * y[k];
-        }
-    }
-    T* D = Dinv + (int64_t)bx * TB * TB;
-#pragma unroll
-    for (int r = 0; r < TB; ++r) D[r + lane * TB] = y[r];
+    InvStep<T, UPPER, 0>::run(y, Ub, rd, Ys);
+    for (int c = 0; c < TB; ++c) D[lane + c * TB] = Ys[lane * TBL + c];
 }
 
 // x (in LDS) := U^{-1} x using the inverted diagonal blocks Dinv of U
-// (stored as by InvDiag for U, or for U^T when dtrans is set,
-// in which case block (r, c) is read as Dinv[c + r*TB]).  U(i, j) =
-// trans ? M[j + i ld] : M[i + j ld]; `lower` says whether U is lower
-// triangular.  `tmp` is LDS scratch of TB elements.  Whole work-group.
+// (stored as by InvDiag for U, or for U^T when dtrans is set, in which case
+// block (r, c) is read as Dinv[c + r*TB]).  U(i, j) = trans ? M[j + i ld] :
+// M[i + j ld]; `lower` says whether U is lower triangular.  `tmp` is LDS
+// scratch of TB elements.  Whole work-group.
 template <typename T>
 __device__ inline void wg_trsv_inv(int64_t n, const T* __restrict__ M, int64_t ld, bool lower, bool trans,
                                    const T* __restrict__ Dinv, bool dtrans, T* x, T* tmp)

@@ -15,21 +15,29 @@ constexpr int TV_MAXN = 4096;   // largest n of the solvers (vector held in LDS)
 size_t dinv_elems(int64_t n) { return (size_t)((n + TB - 1) / TB) * TB * TB; }
 
 template <typename T>
-void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv)
+void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv,
+                     int64_t block0, int64_t nblocks)
 {
-    launch<InvDiag<T>>(ex, (n + TB - 1) / TB, 1, InvDiagArgs{n, M, ld, lower, trans, unit, Dinv});
+    if (nblocks < 0) nblocks = (n + TB - 1) / TB - block0;
+    const InvDiagArgs a{n, M, ld, trans, unit, Dinv, block0};
+    if (lower) launch<InvDiag<T, false>>(ex, nblocks, 1, a);
+    else launch<InvDiag<T, true>>(ex, nblocks, 1, a);
 }
-template void inv_diag_blocks<double>(Exec&, int64_t, const double*, int64_t, int, int, int, double*);
-template void inv_diag_blocks<float>(Exec&, int64_t, const float*, int64_t, int, int, int, float*);
+template void inv_diag_blocks<double>(Exec&, int64_t, const double*, int64_t, int, int, int, double*, int64_t, int64_t);
+template void inv_diag_blocks<float>(Exec&, int64_t, const float*, int64_t, int, int, int, float*, int64_t, int64_t);
 
 // PNE solve in one work-group: L z = c, L^T y = z, R x = y, with the inverted
-// diagonal blocks DL of L and DR of R.
+// diagonal blocks DL of L, DLt of L^T and DR of R.  L^T is read from its
+// explicit copy Lt so that all three matrices are read by columns
+// (contiguous across the threads of the update step).
 struct PneSolve3 {
     struct Args {
         int64_t n;
         const double* L;
         int64_t ldl;
         const double* DL;
+        const double* Lt;
+        const double* DLt;
         const double* R;
         int64_t ldr;
         const double* DR;
@@ -45,16 +53,59 @@ struct PneSolve3 {
         for (int64_t i = threadIdx.x; i < n; i += NTH) xs[i] = a.c[i];
         __syncthreads();
         wg_trsv_inv<double>(n, a.L, a.ldl, true, false, a.DL, false, xs, tmp);
-        wg_trsv_inv<double>(n, a.L, a.ldl, false, true, a.DL, true, xs, tmp);
+        wg_trsv_inv<double>(n, a.Lt, n, false, false, a.DLt, false, xs, tmp);
         wg_trsv_inv<double>(n, a.R, a.ldr, false, false, a.DR, false, xs, tmp);
         for (int64_t i = threadIdx.x; i < n; i += NTH) a.x[i] = xs[i];
     }
 };
 
-void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* R,
-                int64_t ldr, const double* DR, const double* c, double* x)
+void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
+                const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c,
+                double* x)
 {
-    launch<PneSolve3>(ex, 1, 1, PneSolve3::Args{n, L, ldl, DL, R, ldr, DR, c, x});
+    launch<PneSolve3>(ex, 1, 1, PneSolve3::Args{n, L, ldl, DL, Lt, DLt, R, ldr, DR, c, x});
+}
+
+// out(j, i) = in(i, j) through a 64 x 64 LDS tile per work-group.
+struct Transpose {
+    struct Args {
+        int64_t r, c;
+        const double* in;
+        int64_t ldi;
+        double* out;
+        int64_t ldo;
+        int64_t in_stride, out_stride;   // per blockIdx.y (batches of small matrices)
+    };
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by)
+    {
+        __shared__ double t[64 * 65];
+        const int64_t tiles_r = (a.r + 63) / 64;
+        const int64_t i0 = (bx % tiles_r) * 64, j0 = (bx / tiles_r) * 64;
+        const double* __restrict__ in = a.in + by * a.in_stride;
+        double* __restrict__ out = a.out + by * a.out_stride;
+        for (int e = threadIdx.x; e < 64 * 64; e += NTH) {
+            const int ii = e & 63, jj = e >> 6;
+            const int64_t i = i0 + ii, j = j0 + jj;
+            t[jj * 65 + ii] = (i < a.r && j < a.c) ? in[i + j * a.ldi] : 0.0;
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < 64 * 64; e += NTH) {
+            const int jj = e & 63, ii = e >> 6;
+            const int64_t i = i0 + ii, j = j0 + jj;
+            if (i < a.r && j < a.c) out[j + i * a.ldo] = t[jj * 65 + ii];
+        }
+    }
+};
+
+void transpose_f64(Exec& ex, int64_t r, int64_t c, const double* in, int64_t ldi, double* out, int64_t ldo)
+{
+    launch<Transpose>(ex, ceil_div(r, 64) * ceil_div(c, 64), 1, Transpose::Args{r, c, in, ldi, out, ldo, 0, 0});
+}
+
+void transpose_dinv(Exec& ex, int64_t n, const double* D, double* Dt)
+{
+    launch<Transpose>(ex, 1, ceil_div(n, TB), Transpose::Args{TB, TB, D, TB, Dt, TB, TB * TB, TB * TB});
 }
 
 // HPNE solve: x = U^{-1} L^{-1} P c (row exchanges in order, unit lower L),

@@ -7,7 +7,7 @@ import pytest
 import torch
 
 from workloads import make_problem
-from workloads.problems import draw_batch_shapes
+from workloads.problems import draw_batch_shapes, pack_batch
 
 pytestmark = pytest.mark.gpu
 U64 = 2.0 ** -53
@@ -31,21 +31,7 @@ def relerr(x, y):
 
 
 def pack(probs, device="cuda"):
-    """Concatenate the members' A (column-major), b and x slots."""
-    descs, ao, bo, xo = [], 0, 0, 0
-    for p in probs:
-        descs.append(dict(m=p.m, n=p.n, lda=p.m, a_offset=ao, b_offset=bo, x_offset=xo))
-        ao += p.m * p.n
-        bo += p.m
-        xo += p.n
-    A = torch.empty(ao, dtype=torch.float64, device=device)
-    b = torch.empty(bo, dtype=torch.float64, device=device)
-    for p, d in zip(probs, descs):
-        # At (n, m) row-major is A column-major
-        A[d["a_offset"]:d["a_offset"] + p.m * p.n] = p.At.reshape(-1).to(device)
-        b[d["b_offset"]:d["b_offset"] + p.m] = p.b.to(device)
-    x = torch.zeros(xo, dtype=torch.float64, device=device)
-    return A, b, x, descs
+    return pack_batch(probs, device)
 
 
 SHAPES = [(2000, 64, 1e3, 1e-4), (3100, 100, 1e5, 1e-8), (2500, 33, 1e2, 1e-2), (6000, 300, 1e6, 1e-6),

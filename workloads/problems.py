@@ -165,3 +165,25 @@ def make_batch(batch: int = 512, seed: int = 0, device="cpu", shapes=None):
     shapes = draw_batch_shapes(batch, seed) if shapes is None else shapes
     return [make_problem(m, n, kappa, rho, 40000 + i, device=device)
             for i, (m, n, kappa, rho) in enumerate(shapes)]
+
+
+def pack_batch(probs, device="cuda", release=False):
+    """Concatenate the members' A (column-major), b and x slots into flat
+    device buffers.  Returns (A, b, x, descs), descs in the batched solver's
+    format.  With release=True each member's A is dropped once copied."""
+    descs, ao, bo, xo = [], 0, 0, 0
+    for p in probs:
+        descs.append(dict(m=p.m, n=p.n, lda=p.m, a_offset=ao, b_offset=bo, x_offset=xo))
+        ao += p.m * p.n
+        bo += p.m
+        xo += p.n
+    A = torch.empty(ao, dtype=torch.float64, device=device)
+    b = torch.empty(bo, dtype=torch.float64, device=device)
+    for p, d in zip(probs, descs):
+        # At (n, m) row-major is A column-major
+        A[d["a_offset"]:d["a_offset"] + p.m * p.n] = p.At.reshape(-1).to(device)
+        b[d["b_offset"]:d["b_offset"] + p.m] = p.b.to(device)
+        if release:
+            p.At = None
+    x = torch.zeros(xo, dtype=torch.float64, device=device)
+    return A, b, x, descs
