@@ -60,6 +60,14 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const int wm = w & 1, wn = w >> 1;
     const int r16 = lane & 15, g4 = lane >> 4;
 
+    if (PARTIAL && g.xcd_tiles > 0) {
+        // linear id L = bx + T by runs on XCD L % 8; hand that XCD the K
+        // chunks x, x + 8, ... with all T tiles of each chunk together
+        const int64_t T = g.xcd_tiles;
+        const int64_t L = bx + T * by, x = L & 7, q = L >> 3;
+        bx = (int)(q % T);
+        by = (int)(x + 8 * (q / T));
+    }
     int64_t ti, tj;
     const int64_t tiles_m = (g.M + G_BM - 1) / G_BM;
     if (g.lower) lower_tile(bx, ti, tj);

@@ -9,8 +9,8 @@
 //           column needs a single batched reduction, which delivers the norm,
 //           the dot products v^T P(:, j) of the update and the V^T v column of
 //           the triangular factor T (H_1..H_NB = I - V T V^T);
-//   update: Y^T = W_trail^T V (MFMA GEMM, split over rows), Z = T^T Y,
-//           W_trail -= V Z (MFMA GEMM).
+//   update: Y = V^T W_trail, Z = T^T Y, W_trail -= V Z in one kernel (a
+//           wavefront per trailing column).
 // Working precision: FP64 for qr_prec = FP64, FP32 otherwise.  For BF16 and
 // FP16 the input is rounded to the format before the factorization and R_s
 // after it (FP32 arithmetic in between).
@@ -173,7 +173,7 @@ struct QrPanelArgs {
     int w;
     void* W;
     int64_t ldw;
-    void* V;
+    void* V;          // h x NB reflectors, column-major, ld ldv
     int64_t ldv;
     void* Tout;
 };
@@ -213,60 +213,139 @@ __device__ void QrPanel<T, NB, RPT, NT, UNROLL>::run(const QrPanelArgs& a, int, 
         if (r >= h) continue;
 #pragma unroll
         for (int c = 0; c < NB; ++c) {
-            if (c >= w) continue;
             const T val = x[q][c];
-            W[r + c * ldw] = (r <= c) ? val : (T)0;
-            V[r + c * ldv] = (r > c) ? val : (r == c ? (T)1 : (T)0);
+            if (c < w) W[r + c * ldw] = (r <= c) ? val : (T)0;
+            // columns of V past w are zero
+            V[r + c * ldv] = (c >= w) ? (T)0 : ((r > c) ? val : (r == c ? (T)1 : (T)0));
         }
     }
     for (int e = tid; e < NB * NB; e += NT) Tout[(e % NB) + (e / NB) * NB] = sh.Ts[e % NB][e / NB];
 }
 
-// Z(:, j) = T^T sum_z P[z](j, :)^T for each column j of the trailing matrix.
-// P[z] is (rem x w, ld rem) = partial (W_trail^T V).  A work-group handles 16
-// columns: the split partials are summed by (column, entry) threads into LDS,
-// then each (column, entry) thread forms one entry of T^T y.
-struct QrTzArgs {
-    int64_t rem;
-    int w;
-    const void* P;
-    int64_t splits;
-    const void* Tm;
-    void* Z;
+// Trailing update of one panel, W_trail := (I - V T V^T)^T W_trail =
+// W_trail - V (T^T (V^T W_trail)), fused in one kernel.  A work-group owns
+// QU_COLS trailing columns, QU_CPW per wavefront (each V load serves QU_CPW
+// columns); QU_RS wavefronts share each group of columns, lane g of split s
+// walking the rows 64 s + g, 64 s + g + 64 QU_RS, ...:
+//   Y(:, j) = V^T W(:, j)      NB partial dot products per lane, a
+//                              transpose-reduce over the wavefront, then the
+//                              QU_RS partials in a fixed order;
+//   Z(:, j) = T^T Y(:, j)      from LDS;
+//   W(:, j) -= V Z(:, j)       every row again.
+// The row loops are unrolled so that the loads of several rows are in flight
+// together.  Sums run in a fixed order (bitwise reproducible).
+constexpr int QU_WAVES = 8, QU_RS = 2, QU_CPW = 4, QU_COLS = QU_WAVES / QU_RS * QU_CPW;
+struct QrUpdateArgs {
+    int64_t h, rem;
+    void* W;          // trailing matrix, h x rem, column-major
+    int64_t ldw;
+    const void* V;    // h x NB, column-major, ld ldv
+    int64_t ldv;
+    const void* Tm;   // NB x NB upper triangular, column-major
 };
+
+// Sum of v[0..NB) over the 64 lanes: the result for entry e lands in the
+// lanes with (lane >> (6 - LOGNB)) & (NB - 1) == e and is written to out[e].
 template <typename T, int NB>
-struct QrTz {
-    typedef QrTzArgs Args;
-    static constexpr int NTH = 256, WPE = 0;
-    static __device__ void run(const QrTzArgs& a, int bx, int by);
-};
-template <typename T, int NB>
-__device__ void QrTz<T, NB>::run(const QrTzArgs& a, int bx, int)
+__device__ __forceinline__ void wave_transpose_sum(T (&v)[NB], T* out)
 {
-    const int64_t rem = a.rem, splits = a.splits;
-    const int w = a.w;
-    const T* __restrict__ P = (const T*)a.P;
-    const T* __restrict__ Tm = (const T*)a.Tm;
-    T* __restrict__ Z = (T*)a.Z;
-    __shared__ T Ts[NB * NB];
-    __shared__ T ys[NB][16];
-    for (int e = threadIdx.x; e < NB * NB; e += 256) Ts[e] = Tm[e];
-    const int jl = threadIdx.x & 15;
-    const int64_t j = (int64_t)bx * 16 + jl;
-    for (int l = threadIdx.x >> 4; l < NB; l += 16) {
-        T s = 0;
-        if (j < rem && l < w)
-            for (int64_t z = 0; z < splits; ++z) s += P[z * rem * w + j + (int64_t)l * rem];
-        ys[l][jl] = s;
+    constexpr int LOGNB = (NB == 16) ? 4 : 3;
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int step = 0; step < LOGNB; ++step) {
+        const int o = 32 >> step;
+        const int half = NB >> (step + 1);
+        const bool hi = (lane & o) != 0;
+#pragma unroll
+        for (int i = 0; i < half; ++i) {
+            const T lo_sum = v[i] + __shfl_xor(v[i], o, 64);
+            const T hi_sum = v[i + half] + __shfl_xor(v[i + half], o, 64);
+            v[i] = hi ? hi_sum : lo_sum;
+        }
     }
-    __syncthreads();
-    for (int i = threadIdx.x >> 4; i < NB; i += 16) {
-        if (j >= rem || i >= w) continue;
-        T s = 0;
-        for (int l = 0; l <= i; ++l) s += Ts[l + i * NB] * ys[l][jl];
-        Z[i + j * NB] = s;
-    }
+    T y = v[0];
+#pragma unroll
+    for (int o = (32 >> LOGNB); o >= 1; o >>= 1) y += __shfl_xor(y, o, 64);
+    const int idx = (lane >> (6 - LOGNB)) & (NB - 1);
+    if ((lane & ((64 >> LOGNB) - 1)) == 0) out[idx] = y;
 }
+
+template <typename T, int NB>
+struct QrUpdate {
+    typedef QrUpdateArgs Args;
+    static constexpr int NTH = 64 * QU_WAVES, WPE = 0;
+    static __device__ void run(const QrUpdateArgs& a, int bx, int)
+    {
+        __shared__ T Ts[NB * NB];
+        __shared__ T yp[QU_WAVES][QU_CPW][NB];
+        __shared__ T zs[QU_COLS][NB];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int cg = wv / QU_RS, rs = wv % QU_RS;
+        for (int e = threadIdx.x; e < NB * NB; e += NTH) Ts[e] = ((const T*)a.Tm)[e];
+        const int64_t j0 = (int64_t)bx * QU_COLS + cg * QU_CPW;
+        const T* __restrict__ V = (const T*)a.V;
+        T* __restrict__ W = (T*)a.W;
+        const int64_t h = a.h, ldv = a.ldv, ldw = a.ldw, rem = a.rem;
+        int64_t col[QU_CPW];
+#pragma unroll
+        for (int q = 0; q < QU_CPW; ++q) col[q] = ((j0 + q < rem) ? j0 + q : rem - 1) * ldw;
+        constexpr int STRIDE = 64 * QU_RS;
+        const int64_t r0 = 64 * rs + lane;
+        T v[QU_CPW][NB];
+#pragma unroll
+        for (int q = 0; q < QU_CPW; ++q)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) v[q][c] = 0;
+#pragma unroll 2
+        for (int64_t r = r0; r < h; r += STRIDE) {
+            T vr[NB], wr[QU_CPW];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) vr[c] = V[r + c * ldv];
+#pragma unroll
+            for (int q = 0; q < QU_CPW; ++q) wr[q] = W[r + col[q]];
+#pragma unroll
+            for (int q = 0; q < QU_CPW; ++q)
+#pragma unroll
+                for (int c = 0; c < NB; ++c) v[q][c] += vr[c] * wr[q];
+        }
+#pragma unroll
+        for (int q = 0; q < QU_CPW; ++q) wave_transpose_sum<T, NB>(v[q], yp[wv][q]);
+        __syncthreads();
+        for (int t = threadIdx.x; t < QU_COLS * NB; t += NTH) {
+            const int cj = t / NB, i = t % NB;
+            const int g = cj / QU_CPW, q = cj % QU_CPW;
+            T z = 0;
+            for (int l = 0; l <= i; ++l) {
+                T y = 0;
+#pragma unroll
+                for (int p = 0; p < QU_RS; ++p) y += yp[g * QU_RS + p][q][l];
+                z += Ts[l + i * NB] * y;
+            }
+            zs[cj][i] = z;
+        }
+        __syncthreads();
+        T z[QU_CPW][NB];
+#pragma unroll
+        for (int q = 0; q < QU_CPW; ++q)
+#pragma unroll
+            for (int c = 0; c < NB; ++c) z[q][c] = zs[cg * QU_CPW + q][c];
+#pragma unroll 2
+        for (int64_t r = r0; r < h; r += STRIDE) {
+            T vr[NB], wr[QU_CPW];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) vr[c] = V[r + c * ldv];
+#pragma unroll
+            for (int q = 0; q < QU_CPW; ++q) wr[q] = W[r + col[q]];
+#pragma unroll
+            for (int q = 0; q < QU_CPW; ++q) {
+                T s = 0;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) s += vr[c] * z[q][c];
+                if (j0 + q < rem) W[r + col[q]] = wr[q] - s;
+            }
+        }
+    }
+};
 
 struct RoundMatrixArgs {
     int64_t rows, cols;
@@ -365,8 +444,8 @@ __device__ void RDiagCheck::run(const Args& a, int, int)
     }
 }
 
-// Panel width per factorization: 16, except FP64 sketches taller than 2048
-// rows, which use 8 (register budget of the panel kernel).
+// Widest panel of a factorization: 16, except FP64 sketches taller than 2048
+// rows, which use 8 throughout (register budget of the panel kernel).
 template <typename T>
 static int qr_nb(int64_t s)
 {
@@ -374,24 +453,28 @@ static int qr_nb(int64_t s)
     return (sizeof(T) == 8 && s > 2048) ? 8 : 16;
 }
 
+// Width of the panel at height h: FP32 panels taller than 2304 rows use 8
+// columns (the 16-column panel kernel would spill registers there).
+template <typename T>
+static int panel_nb(int64_t s, int64_t h)
+{
+    const int nb = qr_nb<T>(s);
+    return (sizeof(T) == 4 && h > 2304) ? 8 : nb;
+}
+
 bool qr_supported(int64_t s, int prec)
 {
     return prec == PNE_PREC_FP64 ? qr_nb<double>(s) > 0 : qr_nb<float>(s) > 0;
 }
 
-// upper bound of plan_splitk(h, tiles) over all panels (h <= s)
-static int64_t qr_max_splits(int64_t s) { return (s / 128 > 1 ? s / 128 : 1) + 1; }
-
 template <typename T>
 static size_t qr_bytes(int64_t s, int64_t n)
 {
     const int nb = qr_nb<T>(s) ? qr_nb<T>(s) : 8;
-    const int64_t splits = qr_max_splits(s);
     Arena ar(nullptr, 0);
     ar.take<T>((size_t)s * nb);          // V
     ar.take<T>((size_t)nb * nb);         // T
-    ar.take<T>((size_t)splits * n * nb); // partials of W^T V
-    ar.take<T>((size_t)nb * n);          // Z
+    (void)n;
     return ar.used;
 }
 
@@ -408,17 +491,19 @@ static void panel_launch(Exec& ex, int64_t h, int w, T* Wp, int64_t ldw, T* V, i
 
 // Panel shapes (rows per thread, threads, unrolled column loop): the
 // smallest instantiation covering the panel height; unrolled only where the
-// compiled kernel is free of register spills.
+// compiled kernel is free of register spills (FP32: 16-column panels up to
+// 2304 rows, 8-column panels above).
 template <typename T, int NB>
 static void panel_dispatch(Exec& ex, int64_t h, int w, T* Wp, int64_t ldw, T* V, int64_t ldv, T* Tm)
 {
-    if constexpr (sizeof(T) == 4) {
+    if constexpr (sizeof(T) == 4 && NB == 8) {
+        if (h <= 3072) panel_launch<T, NB, 4, 768, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else if (h <= 4096) panel_launch<T, NB, 8, 512, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else panel_launch<T, NB, 12, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+    } else if constexpr (sizeof(T) == 4) {
         if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else if (h <= 2048) panel_launch<T, NB, 2, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
-        else if (h <= 2304) panel_launch<T, NB, 3, 768, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
-        else if (h <= 3072) panel_launch<T, NB, 6, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
-        else if (h <= 4096) panel_launch<T, NB, 8, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
-        else panel_launch<T, NB, 12, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
+        else panel_launch<T, NB, 3, 768, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
     } else if constexpr (NB == 16) {
         if (h <= 1024) panel_launch<T, NB, 1, 1024, true>(ex, h, w, Wp, ldw, V, ldv, Tm);
         else panel_launch<T, NB, 4, 512, false>(ex, h, w, Wp, ldw, V, ldv, Tm);
@@ -436,54 +521,32 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
 {
     if (work_bytes < qr_bytes<T>(s, n)) return PNE_EWORKSPACE;
     const int NBv = qr_nb<T>(s);
-    if (!NBv) return PNE_ENOTSUP;
-    const int64_t splits_max = qr_max_splits(s);
+    if (!NBv) return PNE_ENOTSUP;   // V holds up to NBv columns
     Arena ar(work, work_bytes);
     T* V = ar.take<T>((size_t)s * NBv);
     T* Tm = ar.take<T>((size_t)NBv * NBv);
-    T* P = ar.take<T>((size_t)splits_max * n * NBv);
-    T* Z = ar.take<T>((size_t)NBv * n);
     ex.stage(ST_QR_ROUND);
     if constexpr (sizeof(T) == 4) {
         if (prec == PNE_PREC_BF16 || prec == PNE_PREC_FP16)
             launch<RoundMatrix<T>>(ex, ceil_div(s * n, 256), 1, RoundMatrixArgs{s, n, W, ldw, prec});
     }
     ex.stage(ST_QR);
-    for (int64_t c0 = 0; c0 < n; c0 += NBv) {
-        ex.iter((uint32_t)(c0 / NBv));
-        const int w = (int)((n - c0 < NBv) ? n - c0 : NBv);
+    int64_t c0 = 0;
+    while (c0 < n) {
+        ex.iter((uint32_t)c0);
         const int64_t h = s - c0;
+        const int nb = panel_nb<T>(s, h);
+        const int w = (int)((n - c0 < nb) ? n - c0 : nb);
         T* Wp = W + c0 + c0 * ldw;
-        if (NBv == 16) panel_dispatch<T, 16>(ex, h, w, Wp, ldw, V, s, Tm);
+        if (nb == 16) panel_dispatch<T, 16>(ex, h, w, Wp, ldw, V, s, Tm);
         else panel_dispatch<T, 8>(ex, h, w, Wp, ldw, V, s, Tm);
         const int64_t rem = n - c0 - w;
-        if (rem <= 0) break;
-        T* Wt = W + c0 + (c0 + w) * ldw;
-        // P[z] = (W_trail^T V) over row chunks  (rem x w); at most
-        // qr_max_splits(s) chunks (the partial buffer is sized for that)
-        GemmArgs g{};
-        g.M = rem; g.N = w; g.K = h;
-        g.A = Wt; g.lda = ldw; g.transA = 1;
-        g.B = V; g.ldb = s; g.transB = 0;
-        int64_t splits, kc;
-        plan_splitk(h, ceil_div(rem, 128), &splits, &kc, ex.kchunk_fixed ? 512 : 0);
-        g.splits = splits; g.kchunk = kc;
-        g.P = P;
-        if constexpr (sizeof(T) == 8) gemm_f64_partials(ex, g);
-        else gemm_f32_partials(ex, g);
-        const QrTzArgs ta{rem, w, P, splits, Tm, Z};
-        if (NBv == 16) launch<QrTz<T, 16>>(ex, ceil_div(rem, 16), 1, ta);
-        else launch<QrTz<T, 8>>(ex, ceil_div(rem, 16), 1, ta);
-        // W_trail -= V Z
-        GemmArgs u{};
-        u.M = h; u.N = rem; u.K = w;
-        u.A = V; u.lda = s; u.transA = 0;
-        u.B = Z; u.ldb = NBv; u.transB = 0;
-        u.alpha = -1.0; u.beta = 1.0;
-        u.Cin = Wt; u.ldcin = ldw; u.C = Wt; u.ldc = ldw;
-        u.splits = 1;
-        if constexpr (sizeof(T) == 8) gemm_f64(ex, u);
-        else gemm_f32(ex, u);
+        if (rem > 0) {
+            const QrUpdateArgs u{h, rem, W + c0 + (c0 + w) * ldw, ldw, V, s, Tm};
+            if (nb == 16) launch<QrUpdate<T, 16>>(ex, ceil_div(rem, QU_COLS), 1, u);
+            else launch<QrUpdate<T, 8>>(ex, ceil_div(rem, QU_COLS), 1, u);
+        }
+        c0 += w;
     }
     ex.stage(ST_QR_EXTRACT);
     launch<ExtractR<T>>(ex, ceil_div(n * n, 256), 1, ExtractRArgs{n, W, ldw, prec, R, ldr});
