@@ -59,6 +59,7 @@ struct Buffers {
     double* dinv2;      // block inverses: R_s (PNE) or U (HPNE)
     double* Lt;         // PNE: L^T (n x n)
     double* dinv1t;     // PNE: block inverses of L^T
+    int32_t* flags;     // block flags of the triangular solves
     float* k0;          // condition estimate
     int32_t* choice;
 };
@@ -113,6 +114,7 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
         b.Lt = ar.take<double>((size_t)p.n * p.n);
         b.dinv1t = ar.take<double>(dinv_elems(p.n));
     }
+    b.flags = ar.take<int32_t>(3 * lb_flag_words(p.n));
     if (own_k0) {
         b.k0 = ar.take<float>(4);
         b.choice = ar.take<int32_t>(4);
@@ -255,16 +257,16 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     }
     mark(ex, PH_FACTOR);
     ex.stage(ST_SOLVE);
-    if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx);
-    else pne_solve3(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx);
+    if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, b.flags);
+    else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx, b.flags);
     mark(ex, PH_SOLVE);
     ex.stage(ST_REFINE);
     for (int k = 0; k < p.refine; ++k) {
         ex.iter((uint32_t)k);
         residual(ex, m, n, dA, lda, db, dx, b.r);
         gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
-        if (hpne) lu_solve2(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d);
-        else pne_solve3(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d);
+        if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, b.flags);
+        else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.flags);
         axpy_update(ex, n, dx, b.d);
     }
     ex.stage(ST_FINISH);

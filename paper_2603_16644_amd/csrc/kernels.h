@@ -88,9 +88,11 @@ void trsm_right_upper(Exec& ex, int64_t m, int64_t n, const double* A, int64_t l
                       int64_t ldr, double* Ap, int64_t ldap);
 // row-parallel substitution on a block of <= 64 columns: X := X R^{-1}
 // (R upper, TL = false) or X := X L^{-T} (L lower, TL = true); element
-// (i, c) of X at X[i*rs + c*cs]; UNIT: unit diagonal
+// (i, c) of X at X[i*rs + c*cs]; UNIT: unit diagonal.  With Xin the input is
+// read from Xin[i*rs + c*cs_in] (X is then output only).
 template <typename T, bool TL, bool UNIT>
-void trsm_leaf(Exec& ex, int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr);
+void trsm_leaf(Exec& ex, int64_t m, int w, T* X, int64_t rs, int64_t cs, const T* Rb, int64_t ldr,
+               const T* Xin = nullptr, int64_t cs_in = 0);
 // Cholesky (lower, in place) of the n x n matrix C; info word gets 2000+k.
 // Dinv (dinv_elems(n) values) receives the inverses of the 64 x 64 diagonal
 // blocks of L in the layout of inv_diag_blocks.
@@ -123,6 +125,15 @@ void lu_solve2(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t*
 void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                 const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c,
                 double* x);
+// The same solves with one work-group per 64-row block and per-block flags
+// (flags: 3 * lb_flag_words(n) int32 for the PNE solve, 2 * ... for the LU
+// solve; any contents on entry).  c and x may alias.
+size_t lb_flag_words(int64_t n);
+void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
+                  const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
+                  int32_t* flags);
+void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
+                 const double* DU, const double* c, double* x, int32_t* flags);
 // out (c x r, ldo) = in^T (in r x c, ldi)
 void transpose_f64(Exec& ex, int64_t r, int64_t c, const double* in, int64_t ldi, double* out, int64_t ldo);
 // transposes of the 64 x 64 blocks of a block-inverse array (dinv_elems(n))

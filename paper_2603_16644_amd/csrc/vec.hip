@@ -108,6 +108,159 @@ void transpose_dinv(Exec& ex, int64_t n, const double* D, double* Dt)
     launch<Transpose>(ex, 1, ceil_div(n, TB), Transpose::Args{TB, TB, D, TB, Dt, TB, TB * TB, TB * TB});
 }
 
+// ---------------------------------------------------------------- multi-work-group triangular solve
+// x := U^{-1} x for a triangular n x n matrix U (column-major, lower or
+// upper) with the inverses D of its 64 x 64 diagonal blocks (InvDiag
+// layout), one work-group per block of 64 rows.  Work-groups take their
+// block in dependency order from a ticket counter (forward for lower,
+// backward for upper), so every block they wait for belongs to a
+// work-group that is already running.  A work-group accumulates
+// U(b, j) x_j over the finished blocks j as their flags are raised,
+// forms x_b = D_b (c_b - sum), publishes x_b and raises its own flag.
+// flags[0] is the ticket counter and flags[1 + b] the flag of block b; all
+// must be zero at launch.  Waits are bounded: a flag that is not raised
+// within about 2^24 polls is passed over (the result is then invalid, but
+// the kernel ends).
+constexpr int LB_THREADS = 256;
+
+__device__ __forceinline__ void lb_wait(int32_t* f)
+{
+    for (uint32_t it = 0; it < (1u << 24); ++it) {
+        if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
+        __builtin_amdgcn_s_sleep(1);
+    }
+}
+
+struct TrsvLB {
+    struct Args {
+        int64_t n;
+        const double* M;
+        int64_t ld;
+        int lower;
+        const double* D;
+        double* x;          // in: right-hand side; out: solution
+        int32_t* flags;     // 1 + ceil(n / 64) words, zero at launch
+    };
+    static constexpr int NTH = LB_THREADS, WPE = 0;
+    static __device__ void run(const Args& a, int, int)
+    {
+        __shared__ int32_t tk;
+        __shared__ double xs[TB];
+        __shared__ double red[4][TB];
+        __shared__ double vb[TB];
+        const int tid = threadIdx.x, i = tid & 63, p = tid >> 6;
+        const int64_t n = a.n, nb = (n + TB - 1) / TB;
+        if (tid == 0) tk = atomicAdd(a.flags, 1);
+        __syncthreads();
+        const int64_t t = tk;
+        const int64_t b = a.lower ? t : nb - 1 - t;
+        const int64_t r0 = b * TB;
+        const int bw = (int)((n - r0 < TB) ? n - r0 : TB);
+        const double* __restrict__ M = a.M;
+        double s = 0.0;
+        for (int64_t q = 0; q < t; ++q) {
+            const int64_t j = a.lower ? q : nb - 1 - q;
+            const int64_t c0 = j * TB;
+            const int jw = (int)((n - c0 < TB) ? n - c0 : TB);
+            if (tid == 0) lb_wait(a.flags + 1 + j);
+            __syncthreads();
+            if (tid < TB)
+                xs[tid] = (tid < jw) ? __hip_atomic_load(a.x + c0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                     : 0.0;
+            __syncthreads();
+            if (i < bw) {
+                double mv[16];
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) {
+                    const int k = 16 * p + kk;
+                    mv[kk] = (k < jw) ? M[(r0 + i) + (c0 + k) * a.ld] : 0.0;
+                }
+#pragma unroll
+                for (int kk = 0; kk < 16; ++kk) s += mv[kk] * xs[16 * p + kk];
+            }
+            __syncthreads();
+        }
+        red[p][i] = s;
+        __syncthreads();
+        if (tid < TB) vb[tid] = (tid < bw) ? a.x[r0 + tid] - (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) : 0.0;
+        __syncthreads();
+        const double* Db = a.D + b * TB * TB;
+        double u = 0.0;
+        {
+            double dv[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 16 * p + kk;
+                dv[kk] = (k < bw && i < bw) ? Db[i + k * TB] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) u += dv[kk] * vb[16 * p + kk];
+        }
+        red[p][i] = u;
+        __syncthreads();
+        if (tid < bw) {
+            a.x[r0 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+            __threadfence();
+        }
+        __syncthreads();
+        if (tid == 0) __hip_atomic_store(a.flags + 1 + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    }
+};
+
+size_t lb_flag_words(int64_t n) { return (size_t)((n + TB - 1) / TB) + 1; }
+
+static void trsv_lb(Exec& ex, int64_t n, const double* M, int64_t ld, int lower, const double* D, double* x,
+                    int32_t* flags)
+{
+    launch<TrsvLB>(ex, (n + TB - 1) / TB, 1, TrsvLB::Args{n, M, ld, lower, D, x, flags});
+}
+
+// Row exchanges of the LU pivots applied to x in order (one work-group).
+struct ApplyPivots {
+    struct Args {
+        int64_t n;
+        const int32_t* piv;
+        double* x;
+    };
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const Args& a, int, int)
+    {
+        __shared__ double xs[TV_MAXN];
+        for (int64_t k = threadIdx.x; k < a.n; k += NTH) xs[k] = a.x[k];
+        __syncthreads();
+        if (threadIdx.x == 0)
+            for (int64_t k = 0; k < a.n; ++k) {
+                const int64_t p = a.piv[k];
+                if (p != k) { const double t = xs[k]; xs[k] = xs[p]; xs[p] = t; }
+            }
+        __syncthreads();
+        for (int64_t k = threadIdx.x; k < a.n; k += NTH) a.x[k] = xs[k];
+    }
+};
+
+void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
+                  const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
+                  int32_t* flags)
+{
+    const int64_t fw = (int64_t)lb_flag_words(n);
+    zero_i32(ex, 3 * fw, flags);
+    if (c != x) copy_f64(ex, n, 1, c, n, x, n);
+    trsv_lb(ex, n, L, ldl, 1, DL, x, flags);
+    trsv_lb(ex, n, Lt, n, 0, DLt, x, flags + fw);
+    trsv_lb(ex, n, R, ldr, 0, DR, x, flags + 2 * fw);
+}
+
+void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
+                 const double* DU, const double* c, double* x, int32_t* flags)
+{
+    const int64_t fw = (int64_t)lb_flag_words(n);
+    zero_i32(ex, 2 * fw, flags);
+    if (c != x) copy_f64(ex, n, 1, c, n, x, n);
+    launch<ApplyPivots>(ex, 1, 1, ApplyPivots::Args{n, piv, x});
+    trsv_lb(ex, n, LU, ld, 1, DL, x, flags);
+    trsv_lb(ex, n, LU, ld, 0, DU, x, flags + fw);
+}
+
 // HPNE solve: x = U^{-1} L^{-1} P c (row exchanges in order, unit lower L),
 // with the inverted diagonal blocks DL (unit lower) and DU (upper).
 struct LuSolve {
