@@ -2,7 +2,6 @@
 // sequences of Algorithm 1 for PNE and HPNE.  Everything runs on the
 // caller's stream from the caller's workspace; nothing here allocates.
 #include <math.h>
-#include <stdlib.h>
 #include <string.h>
 
 #include <vector>
@@ -216,16 +215,6 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     int64_t splits, kc;
     const int64_t gtiles = gemm_tiles(n, n, !hpne, 128);
     plan_splitk(m, gtiles, &splits, &kc, ex.kchunk_fixed);
-    int64_t xcd = 0;
-    if (!ex.recording()) {
-        const char* e = getenv("PNE_GRAM_SPLITS");
-        if (e && atoi(e) > 0) {
-            splits = atoi(e);
-            kc = ((m + splits - 1) / splits + 15) / 16 * 16;
-            splits = (m + kc - 1) / kc;
-            if (splits % 8 == 0 && getenv("PNE_GRAM_XCD")) xcd = gtiles;
-        }
-    }
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;
     g.A = b.Ap; g.lda = m; g.transA = 1;
@@ -237,7 +226,6 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     g.P = b.scratch;
     g.Pc = (double*)b.scratch + (size_t)splits * n * n;
     g.bvec = db; g.cvec = b.c;
-    g.xcd_tiles = xcd;
     gemm_f64_partials(ex, g);
     mark(ex, PH_GRAM_GEMM);
     ex.stage(ST_GRAM_REDUCE);

@@ -60,14 +60,6 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const int wm = w & 1, wn = w >> 1;
     const int r16 = lane & 15, g4 = lane >> 4;
 
-    if (PARTIAL && g.xcd_tiles > 0) {
-        // linear id L = bx + T by runs on XCD L % 8; hand that XCD the K
-        // chunks x, x + 8, ... with all T tiles of each chunk together
-        const int64_t T = g.xcd_tiles;
-        const int64_t L = bx + T * by, x = L & 7, q = L >> 3;
-        bx = (int)(q % T);
-        by = (int)(x + 8 * (q / T));
-    }
     int64_t ti, tj;
     const int64_t tiles_m = (g.M + G_BM - 1) / G_BM;
     if (g.lower) lower_tile(bx, ti, tj);
@@ -85,6 +77,10 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const bool vecA = sizeof(TA) == 8 && ((g.lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
     const bool vecB = sizeof(TB) == 8 && ((g.ldb & 1) == 0) && (((uintptr_t)B & 15) == 0);
 
+    // on a diagonal tile of a lower-triangle product the wavefront with rows
+    // 0..63 and columns 64..127 lies above the diagonal: it skips its MFMAs
+    // (its part of C stays alpha * 0 + beta * Cin)
+    const bool idle = g.lower && BN == G_BM && ti == tj && wm < wn;
     VC acc[4][TN];
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -216,6 +212,7 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
         const TC* bs = Bs[buf];
 #pragma unroll
         for (int kk = 0; kk < G_BK; kk += 4) {
+            if (idle) break;
             TC fa[4], fb[TN];
 #pragma unroll
             for (int t = 0; t < 4; ++t) fa[t] = as[(kk + g4) * LDA_S + wm * 64 + t * 16 + r16];

@@ -65,10 +65,6 @@ struct GemmArgs {
     int64_t splits, kchunk;
     void* P; int accumulate_partials;
     const void* bvec; void* Pc; void* cvec;
-    // > 0 (direct launches with splits % 8 == 0 only): the number of output
-    // tiles; work-groups are renumbered so that all tiles of one K chunk run
-    // on one XCD and share its L2 (work-group i runs on XCD i % 8)
-    int64_t xcd_tiles;
 };
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
 void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce

@@ -347,6 +347,133 @@ struct QrUpdate {
     }
 };
 
+// The same update split over row chunks of QS_ROWS rows, for tall panels:
+//   QrYPart:  P[chunk](:, j) = V(chunk)^T W(chunk, j)   (work-group = chunk x
+//             QS_COLS columns, QS_CPW columns per wavefront, QS_ROWS / 64 rows
+//             per lane with all loads issued together);
+//   QrApply:  Y(:, j) = sum over chunks of P (fixed order), Z = T^T Y, then
+//             W(chunk, j) -= V(chunk) Z(:, j) on the same tiling.
+// Each lane touches a few rows only, so the latency of a pass is a few
+// memory round trips instead of one per row.
+constexpr int QS_ROWS = 256, QS_CPW = 4, QS_WAVES = 4, QS_COLS = QS_CPW * QS_WAVES;
+constexpr int QS_RPL = QS_ROWS / 64;   // rows per lane
+constexpr int64_t QS_SPLIT_MIN = 1024; // panels taller than this use the split update
+struct QrSplitArgs {
+    int64_t h, rem;
+    void* W;          // trailing matrix, h x rem, column-major
+    int64_t ldw;
+    const void* V;    // h x NB, column-major, ld ldv
+    int64_t ldv;
+    const void* Tm;   // NB x NB upper triangular, column-major
+    void* P;          // chunk partials: P[(chunk * rem + j) * NB + c]
+};
+
+template <typename T, int NB>
+struct QrYPart {
+    typedef QrSplitArgs Args;
+    static constexpr int NTH = 64 * QS_WAVES, WPE = 0;
+    static __device__ void run(const QrSplitArgs& a, int bx, int by)
+    {
+        __shared__ T ys[QS_WAVES][QS_CPW][NB];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int64_t rc = bx, j0 = (int64_t)by * QS_COLS + wv * QS_CPW;
+        const T* __restrict__ V = (const T*)a.V;
+        const T* __restrict__ W = (const T*)a.W;
+        const int64_t h = a.h, ldv = a.ldv, ldw = a.ldw, rem = a.rem;
+        T vr[QS_RPL][NB], wr[QS_RPL][QS_CPW];
+#pragma unroll
+        for (int k = 0; k < QS_RPL; ++k) {
+            const int64_t r = rc * QS_ROWS + 64 * k + lane;
+            const bool in = r < h;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) vr[k][c] = in ? V[r + c * ldv] : (T)0;
+#pragma unroll
+            for (int q = 0; q < QS_CPW; ++q) wr[k][q] = (in && j0 + q < rem) ? W[r + (j0 + q) * ldw] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < QS_CPW; ++q) {
+            T v[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) {
+                T t = 0;
+#pragma unroll
+                for (int k = 0; k < QS_RPL; ++k) t += vr[k][c] * wr[k][q];
+                v[c] = t;
+            }
+            wave_transpose_sum<T, NB>(v, ys[wv][q]);
+        }
+        __syncthreads();
+        T* __restrict__ P = (T*)a.P;
+        for (int t = threadIdx.x; t < QS_COLS * NB; t += NTH) {
+            const int cj = t / NB, c = t % NB;
+            const int64_t j = (int64_t)by * QS_COLS + cj;
+            if (j < rem) P[(rc * rem + j) * NB + c] = ys[cj / QS_CPW][cj % QS_CPW][c];
+        }
+    }
+};
+
+template <typename T, int NB>
+struct QrApply {
+    typedef QrSplitArgs Args;
+    static constexpr int NTH = 64 * QS_WAVES, WPE = 0;
+    static __device__ void run(const QrSplitArgs& a, int bx, int by)
+    {
+        __shared__ T Ts[NB * NB];
+        __shared__ T ysum[QS_COLS][NB];
+        __shared__ T zs[QS_COLS][NB];
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int64_t rc = bx, h = a.h, rem = a.rem, ldv = a.ldv, ldw = a.ldw;
+        const int64_t nchunk = (h + QS_ROWS - 1) / QS_ROWS;
+        const T* __restrict__ P = (const T*)a.P;
+        for (int e = threadIdx.x; e < NB * NB; e += NTH) Ts[e] = ((const T*)a.Tm)[e];
+        for (int t = threadIdx.x; t < QS_COLS * NB; t += NTH) {
+            const int cj = t / NB, c = t % NB;
+            const int64_t j = (int64_t)by * QS_COLS + cj;
+            T y = 0;
+            if (j < rem)
+                for (int64_t k = 0; k < nchunk; ++k) y += P[(k * rem + j) * NB + c];
+            ysum[cj][c] = y;
+        }
+        __syncthreads();
+        for (int t = threadIdx.x; t < QS_COLS * NB; t += NTH) {
+            const int cj = t / NB, i = t % NB;
+            T z = 0;
+            for (int l = 0; l <= i; ++l) z += Ts[l + i * NB] * ysum[cj][l];
+            zs[cj][i] = z;
+        }
+        __syncthreads();
+        const int64_t j0 = (int64_t)by * QS_COLS + wv * QS_CPW;
+        const T* __restrict__ V = (const T*)a.V;
+        T* __restrict__ W = (T*)a.W;
+        T vr[QS_RPL][NB], wr[QS_RPL][QS_CPW];
+#pragma unroll
+        for (int k = 0; k < QS_RPL; ++k) {
+            const int64_t r = rc * QS_ROWS + 64 * k + lane;
+            const bool in = r < h;
+#pragma unroll
+            for (int c = 0; c < NB; ++c) vr[k][c] = in ? V[r + c * ldv] : (T)0;
+#pragma unroll
+            for (int q = 0; q < QS_CPW; ++q) wr[k][q] = (in && j0 + q < rem) ? W[r + (j0 + q) * ldw] : (T)0;
+        }
+#pragma unroll
+        for (int q = 0; q < QS_CPW; ++q) {
+            if (j0 + q >= rem) continue;
+            T z[NB];
+#pragma unroll
+            for (int c = 0; c < NB; ++c) z[c] = zs[wv * QS_CPW + q][c];
+#pragma unroll
+            for (int k = 0; k < QS_RPL; ++k) {
+                const int64_t r = rc * QS_ROWS + 64 * k + lane;
+                if (r >= h) continue;
+                T sacc = 0;
+#pragma unroll
+                for (int c = 0; c < NB; ++c) sacc += vr[k][c] * z[c];
+                W[r + (j0 + q) * ldw] = wr[k][q] - sacc;
+            }
+        }
+    }
+};
+
 struct RoundMatrixArgs {
     int64_t rows, cols;
     void* M;
@@ -474,7 +601,7 @@ static size_t qr_bytes(int64_t s, int64_t n)
     Arena ar(nullptr, 0);
     ar.take<T>((size_t)s * nb);          // V
     ar.take<T>((size_t)nb * nb);         // T
-    (void)n;
+    ar.take<T>((size_t)ceil_div(s, QS_ROWS) * n * nb);   // chunk partials of V^T W
     return ar.used;
 }
 
@@ -525,6 +652,7 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
     Arena ar(work, work_bytes);
     T* V = ar.take<T>((size_t)s * NBv);
     T* Tm = ar.take<T>((size_t)NBv * NBv);
+    T* Pq = ar.take<T>((size_t)ceil_div(s, QS_ROWS) * n * NBv);
     ex.stage(ST_QR_ROUND);
     if constexpr (sizeof(T) == 4) {
         if (prec == PNE_PREC_BF16 || prec == PNE_PREC_FP16)
@@ -542,9 +670,23 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
         else panel_dispatch<T, 8>(ex, h, w, Wp, ldw, V, s, Tm);
         const int64_t rem = n - c0 - w;
         if (rem > 0) {
-            const QrUpdateArgs u{h, rem, W + c0 + (c0 + w) * ldw, ldw, V, s, Tm};
-            if (nb == 16) launch<QrUpdate<T, 16>>(ex, ceil_div(rem, QU_COLS), 1, u);
-            else launch<QrUpdate<T, 8>>(ex, ceil_div(rem, QU_COLS), 1, u);
+            T* Wt = W + c0 + (c0 + w) * ldw;
+            if (h > QS_SPLIT_MIN) {
+                // tall: two passes over row chunks
+                const QrSplitArgs u{h, rem, Wt, ldw, V, s, Tm, Pq};
+                const int64_t gx = ceil_div(h, QS_ROWS), gy = ceil_div(rem, QS_COLS);
+                if (nb == 16) {
+                    launch<QrYPart<T, 16>>(ex, gx, gy, u);
+                    launch<QrApply<T, 16>>(ex, gx, gy, u);
+                } else {
+                    launch<QrYPart<T, 8>>(ex, gx, gy, u);
+                    launch<QrApply<T, 8>>(ex, gx, gy, u);
+                }
+            } else {
+                const QrUpdateArgs u{h, rem, Wt, ldw, V, s, Tm};
+                if (nb == 16) launch<QrUpdate<T, 16>>(ex, ceil_div(rem, QU_COLS), 1, u);
+                else launch<QrUpdate<T, 8>>(ex, ceil_div(rem, QU_COLS), 1, u);
+            }
         }
         c0 += w;
     }
