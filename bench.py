@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="mixed path only (profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched measurement")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the 512-problem batched measurement (profiling runs); prints its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain elementwise copy (torch.neg) of 512 MiB first, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -225,6 +227,10 @@ def main():
     from workloads import make_problem
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.batch_only:
+        print("[bench] timing the 512-problem batch", file=sys.stderr, flush=True)
+        print(json.dumps(time_batched(pne, args.steps, args.warmup)))
+        return
     print(f"[bench] generating m={M} n={N} kappa={KAPPA:g} rho={RHO:g}", file=sys.stderr, flush=True)
     prob = make_problem(M, N, KAPPA, RHO, seed=1002, device="cuda")
     torch.cuda.synchronize()

@@ -71,6 +71,7 @@ __device__ __forceinline__ typename Op<OP>::T to_op(float x)
 // ---------------------------------------------------------------- 1. Omega
 // out[i * ldk + k] = Omega(i, k0 + k) in the operand format, i < s, k < kc;
 // zero for kc <= k < ldk.
+constexpr int OMEGA_QUADS = 8;   // row quads per thread
 struct OmegaArgs {
     uint64_t seed;
     uint32_t pid;
@@ -92,25 +93,30 @@ __device__ void OmegaGen<OP>::run(const OmegaArgs& a, int bx, int by)
     const int64_t s = a.s, k0 = a.k0, kc = a.kc, ldk = a.ldk;
     T* __restrict__ out = (T*)a.out;
     const int64_t k = (int64_t)bx * 256 + threadIdx.x;
-    const int64_t q = by;
     if (k >= ldk) return;
-    T v[4];
-    if (k < kc) {
-        Gauss4 g = omega_quad(seed, pid, (uint32_t)q, (uint32_t)(k0 + k));
+    // OMEGA_QUADS quads of rows (4 rows each) per thread, same column k
+    for (int qq = 0; qq < OMEGA_QUADS; ++qq) {
+        const int64_t q = (int64_t)by * OMEGA_QUADS + qq;
+        if (4 * q >= s) break;
+        T v[4];
+        if (k < kc) {
+            Gauss4 g = omega_quad(seed, pid, (uint32_t)q, (uint32_t)(k0 + k));
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = to_op<OP>(g.z[t]);
-    } else {
+            for (int t = 0; t < 4; ++t) v[t] = to_op<OP>(g.z[t]);
+        } else {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) v[t] = (T)0;
-    }
+            for (int t = 0; t < 4; ++t) v[t] = (T)0;
+        }
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int64_t i = 4 * q + t;
-        if (i < s) out[i * ldk + k] = v[t];
+        for (int t = 0; t < 4; ++t) {
+            const int64_t i = 4 * q + t;
+            if (i < s) out[i * ldk + k] = v[t];
+        }
     }
 }
 
 // ---------------------------------------------------------------- 2. quantize A
+constexpr int QUANT_PER = 4;     // rows per thread (unscaled formats)
 // Unscaled formats: Aq[j * ldk + k] = op(A(k0 + k, j)); zero padding.
 struct QuantArgs {
     const double* A;
@@ -127,17 +133,32 @@ struct QuantizePlain {
 template <int OP>
 __device__ void QuantizePlain<OP>::run(const QuantArgs& a, int bx, int by)
 {
+    typedef typename Op<OP>::T T;
     const double* __restrict__ A = a.A;
     const int64_t lda = a.lda, k0 = a.k0, kc = a.kc, ldk = a.ldk;
-    typename Op<OP>::T* __restrict__ Aq = (typename Op<OP>::T*)a.Aq;
-    const int64_t k = (int64_t)bx * 256 + threadIdx.x;
+    T* __restrict__ Aq = (T*)a.Aq;
     const int64_t j = by;
-    if (k >= ldk) return;
-    const float v = (k < kc) ? (float)A[(k0 + k) + j * lda] : 0.0f;
-    Aq[j * ldk + k] = to_op<OP>(v);
+    // QUANT_PER consecutive rows per thread: two 16-byte loads and one
+    // 8-byte store when the column is aligned and the rows are all in range
+    const int64_t kb = ((int64_t)bx * 256 + threadIdx.x) * QUANT_PER;
+    if (kb >= ldk) return;
+    const double* src = A + (k0 + kb) + j * lda;
+    if (sizeof(T) == 2 && kb + QUANT_PER <= kc && (((uintptr_t)src) & 15) == 0) {
+        const double2 v0 = *(const double2*)src, v1 = *(const double2*)(src + 2);
+        const uint32_t q0 = (uint32_t)to_op<OP>((float)v0.x) | ((uint32_t)to_op<OP>((float)v0.y) << 16);
+        const uint32_t q1 = (uint32_t)to_op<OP>((float)v1.x) | ((uint32_t)to_op<OP>((float)v1.y) << 16);
+        *(uint2*)(Aq + j * ldk + kb) = make_uint2(q0, q1);
+        return;
+    }
+#pragma unroll
+    for (int t = 0; t < QUANT_PER; ++t) {
+        const int64_t k = kb + t;
+        if (k >= ldk) break;
+        const float v = (k < kc) ? (float)A[(k0 + k) + j * lda] : 0.0f;
+        Aq[j * ldk + k] = to_op<OP>(v);
+    }
 }
 
-// Block-scaled formats: one work-group per (block of `br` rows, column j).
 template <int OP>
 struct QuantizeScaled {
     typedef QuantArgs Args;
@@ -431,7 +452,7 @@ static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t
                          int64_t kc, int64_t n, int64_t s, uint64_t seed, uint32_t pid, int64_t br,
                          void* Omq, void* Aq, float* sc, void* P, int accumulate)
 {
-    launch<OmegaGen<OP>>(ex, ceil_div(p.ldk, 256), ceil_div(s, 4),
+    launch<OmegaGen<OP>>(ex, ceil_div(p.ldk, 256), ceil_div(ceil_div(s, 4), OMEGA_QUADS),
                          OmegaArgs{seed, pid, s, k0, kc, p.ldk, Omq});
     if (!ex.recording()) prof_mark(PH_SK_OMEGA, ex.st);
     if constexpr (OP == OPK_F64) {
@@ -447,7 +468,7 @@ static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t
         constexpr bool SC = (OP == OPK_FP8 || OP == OPK_F16);
         const QuantArgs q{A, lda, k0, kc, p.ldk, br, n, Aq, sc};
         if constexpr (SC) launch<QuantizeScaled<OP>>(ex, ceil_div(p.ldk, br), n, q);
-        else launch<QuantizePlain<OP>>(ex, ceil_div(p.ldk, 256), n, q);
+        else launch<QuantizePlain<OP>>(ex, ceil_div(p.ldk, 256 * QUANT_PER), n, q);
         if (!ex.recording()) prof_mark(PH_SK_QUANT, ex.st);
         launch<GemmLp<OP, SC>>(ex, ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits,
                                GemmLpArgs{Omq, Aq, p.ldk, s, n, sc, br, (float*)P, p.kchunk, accumulate});
