@@ -70,16 +70,99 @@ template <typename T, int NB, int NT>
 struct PanelShared {
     T red[NT / 64][NB];
     T bc[NB];
-    T cf[NB];      // tau * v^T P(:, c) for c > k
-    T gv[NB];      // V(:, i)^T v for i < k
-    T sc[2];       // 1 / (alpha - beta), tau
+    T rowk[2][NB];     // row k of the panel, published by its owner (two steps alternate)
+    T G[NB][NB + 1];   // G[k][l] = V(:, l)^T v_k for l < k
+    T tauv[NB];
     T Ts[NB][NB + 1];
+    T cf[NB];          // (owner-computed variant) tau v^T P(:, c) for c > k
+    T gv[NB];          // (owner-computed variant) V(:, i)^T v for i < k
+    T sc[2];           // (owner-computed variant) 1 / (alpha - beta), tau
 };
 
-// One column step of the panel (see qr_panel_kernel).  KS >= 0 makes the
-// column index a compile-time constant (KS == k); KS < 0 takes k at run time.
+// Which column-step variant a panel shape uses: the redundant one (two
+// barriers per column) where it compiles free of register spills, the
+// owner-computed one (three barriers, T built column by column) elsewhere.
+template <typename T, int KS>
+constexpr bool panel_redundant() { return KS >= 0 && sizeof(T) == 4; }
+
+// One column step of the panel (see QrPanel).  KS >= 0 makes the column
+// index a compile-time constant (KS == k); KS < 0 takes k at run time.  The
+// owner of row k publishes the row before the reduction, so that every
+// thread forms beta, tau and the update coefficients itself after it: two
+// barriers per column.  The triangular factor T is assembled after the last
+// column from the stored V^T v_k and tau_k.
 template <typename T, int NB, int RPT, int NT, int KS>
-__device__ __forceinline__ void panel_step(int k_rt, int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
+__device__ __forceinline__ void panel_step_redundant(int k_rt, int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
+{
+    const int k = KS >= 0 ? KS : k_rt;
+    const int tid = threadIdx.x;
+    T* rk = sh.rowk[k & 1];
+    if (tid == k) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) rk[c] = x[0][c];
+    }
+    T vals[NB];
+#pragma unroll
+    for (int c = 0; c < NB; ++c) vals[c] = 0;
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + NT * q;
+        T xk = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == k) xk = x[q][c];
+        xk = (r > k) ? xk : (T)0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c) vals[c] += xk * x[q][c];
+    }
+    batched_block_sum<T, NB>(vals, sh.red, sh.bc, NT / 64);
+    // every thread: beta = -sign(alpha) sqrt(alpha^2 + sigma),
+    // tau = (beta - alpha) / beta, v = [1; x(r>k, k) / (alpha - beta)]
+    const T alpha = rk[k], sigma = sh.bc[k];
+    T beta, tau, inv;
+    if (sigma == (T)0) {
+        beta = alpha; tau = 0; inv = 0;
+    } else {
+        const T nrm = sqrt(alpha * alpha + sigma);
+        beta = (alpha >= (T)0) ? -nrm : nrm;
+        tau = (beta - alpha) / beta;
+        inv = (T)1 / (alpha - beta);
+    }
+    T cf[NB];   // tau v^T P(:, c) for the columns c > k
+#pragma unroll
+    for (int c = 0; c < NB; ++c) cf[c] = (c > k && c < w) ? tau * (rk[c] + sh.bc[c] * inv) : (T)0;
+    if (tid == k) {
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c < k) sh.G[k][c] = rk[c] + sh.bc[c] * inv;
+            if (c == k) x[0][c] = beta;
+        }
+        sh.tauv[k] = tau;
+    }
+    // v (stored in place of column k below the diagonal) and the update,
+    // branch free: v_r = 0 above row k, 1 on it, x(r, k) / (alpha - beta) below
+#pragma unroll
+    for (int q = 0; q < RPT; ++q) {
+        const int64_t r = tid + NT * q;
+        T xk = 0;
+#pragma unroll
+        for (int c = 0; c < NB; ++c)
+            if (c == k) xk = x[q][c];
+        const T scaled = xk * inv;
+        const T vr = (r > k) ? scaled : ((r == k) ? (T)1 : (T)0);
+#pragma unroll
+        for (int c = 0; c < NB; ++c) {
+            if (c == k) x[q][c] = (r > k) ? scaled : xk;
+            if (c > k && c < w) x[q][c] -= cf[c] * vr;
+        }
+    }
+}
+
+// Owner-computed variant: the thread owning row k forms beta, tau and the
+// coefficients and publishes them (three barriers per column); T is built
+// column by column.
+template <typename T, int NB, int RPT, int NT, int KS>
+__device__ __forceinline__ void panel_step_owner(int k_rt, int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
 {
     const int k = KS >= 0 ? KS : k_rt;
     const int tid = threadIdx.x;
@@ -131,8 +214,6 @@ __device__ __forceinline__ void panel_step(int k_rt, int w, T (&x)[RPT][NB], Pan
         sh.Ts[tid][k] = -tau * acc;
     }
     if (tid == k) sh.Ts[k][k] = tau;
-    // v (stored in place of column k below the diagonal) and the update,
-    // branch free: v_r = 0 above row k, 1 on it, x(r, k) / (alpha - beta) below
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int64_t r = tid + NT * q;
@@ -148,6 +229,13 @@ __device__ __forceinline__ void panel_step(int k_rt, int w, T (&x)[RPT][NB], Pan
             if (c > k && c < w) x[q][c] -= sh.cf[c] * vr;
         }
     }
+}
+
+template <typename T, int NB, int RPT, int NT, int KS>
+__device__ __forceinline__ void panel_step(int k_rt, int w, T (&x)[RPT][NB], PanelShared<T, NB, NT>& sh)
+{
+    if constexpr (panel_redundant<T, KS>()) panel_step_redundant<T, NB, RPT, NT, KS>(k_rt, w, x, sh);
+    else panel_step_owner<T, NB, RPT, NT, KS>(k_rt, w, x, sh);
 }
 
 // Steps K, K+1, ..., NB-1 with compile-time column indices.
@@ -193,7 +281,9 @@ __device__ void QrPanel<T, NB, RPT, NT, UNROLL>::run(const QrPanelArgs& a, int, 
     T* __restrict__ Tout = (T*)a.Tout;
     __shared__ PanelShared<T, NB, NT> sh;
     const int tid = threadIdx.x;
-    for (int e = tid; e < NB * NB; e += NT) sh.Ts[e / NB][e % NB] = 0;
+    constexpr bool RED = panel_redundant<T, UNROLL ? 0 : -1>();
+    if constexpr (!RED)
+        for (int e = tid; e < NB * NB; e += NT) sh.Ts[e / NB][e % NB] = 0;
     T x[RPT][NB];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -205,6 +295,31 @@ __device__ void QrPanel<T, NB, RPT, NT, UNROLL>::run(const QrPanelArgs& a, int, 
         PanelSteps<T, NB, RPT, NT, 0>::run(w, x, sh);
     } else {
         for (int k = 0; k < w; ++k) panel_step<T, NB, RPT, NT, -1>(k, w, x, sh);
+    }
+    __syncthreads();
+    // T(i, k) = -tau_k sum_{l = i..k-1} T(i, l) (V^T v_k)_l for i < k,
+    // T(k, k) = tau_k: thread i builds row i (it only reads its own row)
+    if (RED && tid < NB) {
+        const int i = tid;
+        T trow[NB];
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) {
+            T v = 0;
+            if (kk < w) {
+                if (kk == i) {
+                    v = sh.tauv[kk];
+                } else if (i < kk) {
+                    T acc = 0;
+#pragma unroll
+                    for (int l = 0; l < kk; ++l)
+                        if (l >= i) acc += trow[l] * sh.G[kk][l];
+                    v = -sh.tauv[kk] * acc;
+                }
+            }
+            trow[kk] = v;
+        }
+#pragma unroll
+        for (int kk = 0; kk < NB; ++kk) sh.Ts[i][kk] = trow[kk];
     }
     __syncthreads();
 #pragma unroll
@@ -430,8 +545,18 @@ struct QrApply {
             const int cj = t / NB, c = t % NB;
             const int64_t j = (int64_t)by * QS_COLS + cj;
             T y = 0;
-            if (j < rem)
-                for (int64_t k = 0; k < nchunk; ++k) y += P[(k * rem + j) * NB + c];
+            if (j < rem) {
+                // loads of 8 chunks issued together, added in chunk order
+                int64_t k = 0;
+                for (; k + 8 <= nchunk; k += 8) {
+                    T pv[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) pv[u] = P[((k + u) * rem + j) * NB + c];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) y += pv[u];
+                }
+                for (; k < nchunk; ++k) y += P[(k * rem + j) * NB + c];
+            }
             ysum[cj][c] = y;
         }
         __syncthreads();
