@@ -106,7 +106,7 @@ def roofline(ph):
     """Dominant single-kernel phase against its MFMA peak (algorithmic flops)."""
     cands = {
         # C = A_p^T A_p (lower triangle incl. diagonal) and c = A_p^T b
-        "gram_gemm": (M * N * (N + 1) + 2 * M * N, PEAK_FP64, "GemmCm<double,double,double,128,true>"),
+        "gram_gemm": (M * N * (N + 1) + 2 * M * N, PEAK_FP64, "GemmCm<double,double,double,128,128,true>"),
         # A_s = Omega A, BF16 operands
         "sketch_gemm": (2 * S * M * N, PEAK_BF16, "GemmLp<bf16,false>"),
     }

@@ -18,7 +18,7 @@
 
 namespace pne {
 
-constexpr int G_BM = 128, G_BK = 16, G_PAD = 16;
+constexpr int G_BK = 16, G_PAD = 16;
 
 template <typename TC>
 __device__ __forceinline__ auto mfma_cm(TC a, TC b,
@@ -37,20 +37,23 @@ __device__ __forceinline__ void lower_tile(int64_t id, int64_t& ti, int64_t& tj)
     tj = id - t * (t + 1) / 2;
 }
 
-template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
+template <typename TA, typename TB, typename TC, int BM, int BN, bool PARTIAL>
 struct GemmCm {
     typedef GemmArgs Args;
-    static constexpr int NTH = 256, WPE = 2;
+    static constexpr int NTH = 256, WPE = BM == 64 ? 3 : 2;
     static __device__ void run(const GemmArgs& g, int bx, int by);
 };
 
-template <typename TA, typename TB, typename TC, int BN, bool PARTIAL>
-__device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, int by)
+template <typename TA, typename TB, typename TC, int BM, int BN, bool PARTIAL>
+__device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int bx, int by)
 {
     typedef typename std::conditional<sizeof(TC) == 8, v4d, v4f>::type VC;
+    constexpr int TM = BM / 32;                // 16-wide MFMA tiles per wave along M
     constexpr int TN = BN / 32;                // 16-wide MFMA tiles per wave along N
-    constexpr int LDA_S = G_BM + G_PAD, LDB_S = BN + G_PAD;
+    constexpr int LDA_S = BM + G_PAD, LDB_S = BN + G_PAD;
+    constexpr int APT = BM / 16;               // A elements per thread per K tile
     constexpr int BPT = BN / 16;               // B elements per thread per K tile
+    constexpr int TPR = 256 / BM;              // threads per row of op(A) (transposed load)
     // two LDS buffers: the tile in use and the next one
     __shared__ TC As[2][G_BK * LDA_S];
     __shared__ TC Bs[2][G_BK * LDB_S];
@@ -61,10 +64,10 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const int r16 = lane & 15, g4 = lane >> 4;
 
     int64_t ti, tj;
-    const int64_t tiles_m = (g.M + G_BM - 1) / G_BM;
+    const int64_t tiles_m = (g.M + BM - 1) / BM;
     if (g.lower) lower_tile(bx, ti, tj);
     else { ti = bx % tiles_m; tj = bx / tiles_m; }
-    const int64_t i0 = ti * G_BM, j0 = tj * BN;
+    const int64_t i0 = ti * BM, j0 = tj * BN;
     const int64_t kbeg = PARTIAL ? (int64_t)by * g.kchunk : 0;
     int64_t kend = PARTIAL ? kbeg + g.kchunk : g.K;
     if (kend > g.K) kend = g.K;
@@ -73,51 +76,51 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const TB* __restrict__ B = (const TB*)g.B;
     const double* __restrict__ bv = (const double*)g.bvec;
     const bool fold = (bv != nullptr) && (tj == 0);
-    // 16-byte vector loads when every run of 8 (A) / BPT (B) elements is aligned
+    // 16-byte vector loads when every run of APT (A) / BPT (B) elements is aligned
     const bool vecA = sizeof(TA) == 8 && ((g.lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
     const bool vecB = sizeof(TB) == 8 && ((g.ldb & 1) == 0) && (((uintptr_t)B & 15) == 0);
 
-    // on a diagonal tile of a lower-triangle product the wavefront with rows
-    // 0..63 and columns 64..127 lies above the diagonal: it skips its MFMAs
-    // (its part of C stays alpha * 0 + beta * Cin)
-    const bool idle = g.lower && BN == G_BM && ti == tj && wm < wn;
-    VC acc[4][TN];
+    // on a diagonal tile of a lower-triangle product the wavefront with the
+    // upper half of the rows and the right half of the columns lies above the
+    // diagonal: it skips its MFMAs (its part of C stays alpha * 0 + beta * Cin)
+    const bool idle = g.lower && BN == BM && ti == tj && wm < wn;
+    VC acc[TM][TN];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < TM; ++a)
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = (VC){0, 0, 0, 0};
     TC cpart = 0;
 
-    TC ra[8], rb[BPT], rbv = 0;
+    TC ra[APT], rb[BPT], rbv = 0;
     // Load the K tile starting at k0 into registers (zero outside the matrix).
     auto gload = [&](int64_t k0) {
         if (!g.transA) {
-            const int kk = tid >> 4, ib = (tid & 15) * 8;
+            const int kk = tid >> 4, ib = (tid & 15) * APT;
             const int64_t k = k0 + kk;
             const TA* p = A + (i0 + ib) + k * g.lda;
-            if (vecA && k < kend && i0 + ib + 8 <= g.M) {
+            if (vecA && k < kend && i0 + ib + APT <= g.M) {
 #pragma unroll
-                for (int q = 0; q < 8; q += 2) {
+                for (int q = 0; q < APT; q += 2) {
                     const double2 v = *(const double2*)(p + q);
                     ra[q] = (TC)v.x; ra[q + 1] = (TC)v.y;
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) ra[q] = (i0 + ib + q < g.M && k < kend) ? (TC)p[q] : (TC)0;
+                for (int q = 0; q < APT; ++q) ra[q] = (i0 + ib + q < g.M && k < kend) ? (TC)p[q] : (TC)0;
             }
         } else {
-            const int ii = tid >> 1, kb = (tid & 1) * 8;
+            const int ii = tid / TPR, kb = (tid % TPR) * APT;
             const int64_t i = i0 + ii;
             const TA* p = A + (k0 + kb) + i * g.lda;
-            if (vecA && i < g.M && k0 + kb + 8 <= kend) {
+            if (vecA && i < g.M && k0 + kb + APT <= kend) {
 #pragma unroll
-                for (int q = 0; q < 8; q += 2) {
+                for (int q = 0; q < APT; q += 2) {
                     const double2 v = *(const double2*)(p + q);
                     ra[q] = (TC)v.x; ra[q + 1] = (TC)v.y;
                 }
             } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) ra[q] = (i < g.M && k0 + kb + q < kend) ? (TC)p[q] : (TC)0;
+                for (int q = 0; q < APT; ++q) ra[q] = (i < g.M && k0 + kb + q < kend) ? (TC)p[q] : (TC)0;
             }
         }
         if (!g.transB) {
@@ -156,13 +159,13 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
         TC* as = As[buf];
         TC* bs = Bs[buf];
         if (!g.transA) {
-            const int kk = tid >> 4, ib = (tid & 15) * 8;
+            const int kk = tid >> 4, ib = (tid & 15) * APT;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) as[kk * LDA_S + ib + q] = ra[q];
+            for (int q = 0; q < APT; ++q) as[kk * LDA_S + ib + q] = ra[q];
         } else {
-            const int ii = tid >> 1, kb = (tid & 1) * 8;
+            const int ii = tid / TPR, kb = (tid % TPR) * APT;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) as[(kb + q) * LDA_S + ii] = ra[q];
+            for (int q = 0; q < APT; ++q) as[(kb + q) * LDA_S + ii] = ra[q];
         }
         if (!g.transB) {
             constexpr int TPC = 256 / BN;
@@ -180,18 +183,18 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     // FP32 products with a single K tile (the QR trailing update, K = panel
     // width): fetch the Cin values of the lane together with the operands.
     constexpr bool PRE = sizeof(TC) == 4 && !PARTIAL;
-    TC pre[PRE ? 4 : 1][PRE ? TN : 1][PRE ? 4 : 1];
+    TC pre[PRE ? TM : 1][PRE ? TN : 1][PRE ? 4 : 1];
     const bool use_pre = PRE && g.Cin != nullptr && (kend - kbeg) <= G_BK;
     if constexpr (PRE) {
         if (use_pre) {
             const TC* Cin0 = (const TC*)g.Cin;
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < TM; ++a)
 #pragma unroll
                 for (int b = 0; b < TN; ++b)
 #pragma unroll
                     for (int r = 0; r < 4; ++r) {
-                        const int64_t i = i0 + wm * 64 + a * 16 + r16;
+                        const int64_t i = i0 + wm * (BM / 2) + a * 16 + r16;
                         const int64_t j = j0 + wn * (BN / 2) + b * 16 + 4 * g4 + r;
                         pre[a][b][r] = (i < g.M && j < g.N) ? Cin0[i + j * g.ldcin] : (TC)0;
                     }
@@ -213,17 +216,17 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
 #pragma unroll
         for (int kk = 0; kk < G_BK; kk += 4) {
             if (idle) break;
-            TC fa[4], fb[TN];
+            TC fa[TM], fb[TN];
 #pragma unroll
-            for (int t = 0; t < 4; ++t) fa[t] = as[(kk + g4) * LDA_S + wm * 64 + t * 16 + r16];
+            for (int t = 0; t < TM; ++t) fa[t] = as[(kk + g4) * LDA_S + wm * (BM / 2) + t * 16 + r16];
 #pragma unroll
             for (int t = 0; t < TN; ++t) fb[t] = bs[(kk + g4) * LDB_S + wn * (BN / 2) + t * 16 + r16];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < TM; ++a)
 #pragma unroll
                 for (int b = 0; b < TN; ++b) acc[a][b] = mfma_cm<TC>(fb[b], fa[a], acc[a][b]);
         }
-        if (fold && tid < G_BM) {
+        if (fold && tid < BM) {
 #pragma unroll
             for (int kk = 0; kk < G_BK; ++kk) cpart += as[kk * LDA_S + tid] * bsh[buf][kk];
         }
@@ -245,8 +248,8 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
     const TC* src = PARTIAL ? (g.accumulate_partials ? P : nullptr) : Cin;
     const int64_t lds_ = PARTIAL ? g.M : g.ldcin;
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t i = i0 + wm * 64 + a * 16 + r16;
+    for (int a = 0; a < TM; ++a) {
+        const int64_t i = i0 + wm * (BM / 2) + a * 16 + r16;
         TC prev[TN][4];
 #pragma unroll
         for (int b = 0; b < TN; ++b)
@@ -269,7 +272,7 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
                 else C[i + j * g.ldc] = (TC)g.alpha * acc[a][b][r] + (TC)g.beta * prev[b][r];
             }
     }
-    if (fold && tid < G_BM && i0 + tid < g.M) {
+    if (fold && tid < BM && i0 + tid < g.M) {
         if (PARTIAL) ((TC*)g.Pc)[(int64_t)by * g.M + i0 + tid] = cpart;
         else ((TC*)g.cvec)[i0 + tid] = cpart;
     }
@@ -277,7 +280,7 @@ __device__ void GemmCm<TA, TB, TC, BN, PARTIAL>::run(const GemmArgs& g, int bx, 
 
 struct GemmReduceArgs {
     GemmArgs g;
-    int bn;
+    int bm, bn;
 };
 template <typename TC>
 struct GemmReduce {
@@ -289,12 +292,12 @@ template <typename TC>
 __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
 {
     const GemmArgs& g = a.g;
-    const int bn = a.bn;
+    const int bm = a.bm, bn = a.bn;
     const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     const TC* P = (const TC*)g.P;
     if (idx < g.M * g.N) {
         const int64_t i = idx % g.M, j = idx / g.M;
-        if (!g.lower || (i / G_BM) >= (j / bn)) {
+        if (!g.lower || (i / bm) >= (j / bn)) {
             TC s = 0;
             for (int64_t z = 0; z < g.splits; ++z) s += P[z * g.M * g.N + idx];
             TC v = (TC)g.alpha * s;
@@ -309,10 +312,23 @@ __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
     }
 }
 
-int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn)
+// Output tile of a product: 128 x 128 in general; 128 x 64 for narrow
+// products (N <= 64); 64 x 64 for lower-triangle products of order <= 512,
+// where 128-wide tiles would spend a large share of their work on padding.
+struct TileShape {
+    int bm, bn;
+};
+static TileShape tile_shape(int64_t, int64_t N, int lower)
 {
-    const int64_t tm = ceil_div(M, G_BM), tn = ceil_div(N, bn);
-    if (lower) return tm * (tm + 1) / 2;  // requires bn == G_BM and square problems
+    if (lower) return N <= 512 ? TileShape{64, 64} : TileShape{128, 128};
+    return N <= 64 ? TileShape{128, 64} : TileShape{128, 128};
+}
+
+int64_t gemm_tiles(int64_t M, int64_t N, int lower)
+{
+    const TileShape ts = tile_shape(M, N, lower);
+    const int64_t tm = ceil_div(M, ts.bm), tn = ceil_div(N, ts.bn);
+    if (lower) return tm * (tm + 1) / 2;  // square tiles, square problems
     return tm * tn;
 }
 
@@ -350,37 +366,43 @@ void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int
 }
 
 template <typename TC>
-static void gemm_reduce_launch(Exec& ex, const GemmArgs& g, int bn)
+static void gemm_reduce_launch(Exec& ex, const GemmArgs& g)
 {
+    const TileShape ts = tile_shape(g.M, g.N, g.lower);
     int64_t cnt = g.M * g.N;
     if (g.bvec && g.M > cnt) cnt = g.M;
-    launch<GemmReduce<TC>>(ex, ceil_div(cnt, 256), 1, GemmReduceArgs{g, bn});
+    launch<GemmReduce<TC>>(ex, ceil_div(cnt, 256), 1, GemmReduceArgs{g, ts.bm, ts.bn});
+}
+
+template <typename TA, typename TB, typename TC, bool PARTIAL>
+static void gemm_tiles_launch(Exec& ex, const TileShape& ts, int64_t tiles, const GemmArgs& g)
+{
+    if (ts.bm == 64) launch<GemmCm<TA, TB, TC, 64, 64, PARTIAL>>(ex, tiles, g.splits, g);
+    else if (ts.bn == 64) launch<GemmCm<TA, TB, TC, 128, 64, PARTIAL>>(ex, tiles, g.splits, g);
+    else launch<GemmCm<TA, TB, TC, 128, 128, PARTIAL>>(ex, tiles, g.splits, g);
 }
 
 template <typename TA, typename TB, typename TC>
 static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
 {
     GemmArgs g = g0;
-    const bool narrow = !g.lower && g.N <= 64;
-    const int bn = narrow ? 64 : 128;
-    const int64_t tiles = gemm_tiles(g.M, g.N, g.lower, bn);
+    const TileShape ts = tile_shape(g.M, g.N, g.lower);
+    const int64_t tiles = gemm_tiles(g.M, g.N, g.lower);
     if (tiles == 0) return;
     const bool partial = g.splits > 1 || !reduce;
     if (!partial) {
         g.splits = 1;
-        if (narrow) launch<GemmCm<TA, TB, TC, 64, false>>(ex, tiles, 1, g);
-        else launch<GemmCm<TA, TB, TC, 128, false>>(ex, tiles, 1, g);
+        gemm_tiles_launch<TA, TB, TC, false>(ex, ts, tiles, g);
         return;
     }
     if (g.splits < 1) g.splits = 1;
     if (g.kchunk <= 0) g.kchunk = ceil_div(ceil_div(g.K, g.splits), G_BK) * G_BK;
-    if (narrow) launch<GemmCm<TA, TB, TC, 64, true>>(ex, tiles, g.splits, g);
-    else launch<GemmCm<TA, TB, TC, 128, true>>(ex, tiles, g.splits, g);
-    if (reduce) gemm_reduce_launch<TC>(ex, g, bn);
+    gemm_tiles_launch<TA, TB, TC, true>(ex, ts, tiles, g);
+    if (reduce) gemm_reduce_launch<TC>(ex, g);
 }
 
 void gemm_f64(Exec& ex, const GemmArgs& g) { gemm_launch<double, double, double>(ex, g, true); }
-void gemm_f64_reduce(Exec& ex, const GemmArgs& g) { gemm_reduce_launch<double>(ex, g, 128); }
+void gemm_f64_reduce(Exec& ex, const GemmArgs& g) { gemm_reduce_launch<double>(ex, g); }
 void gemm_f64_partials(Exec& ex, const GemmArgs& g) { gemm_launch<double, double, double>(ex, g, false); }
 void gemm_f32(Exec& ex, const GemmArgs& g) { gemm_launch<float, float, float>(ex, g, true); }
 void gemm_f32_partials(Exec& ex, const GemmArgs& g) { gemm_launch<float, float, float>(ex, g, false); }

@@ -51,7 +51,7 @@ int sketch_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int
 // Column-major C = alpha op(A) op(B) + beta Cin (C may alias Cin).
 // With splits > 1 the raw products go to partial buffers P[z] (M x N, ld M)
 // and gemm_reduce_* forms C.  `lower` restricts work to output tiles on or
-// below the diagonal (square 128 x 128 tiles).  With bvec != null the
+// below the diagonal (square tiles).  With bvec != null the
 // work-groups of the first tile column also form op(A) bvec into Pc[z]
 // (n-vector partials), reduced into cvec.
 struct GemmArgs {
@@ -69,14 +69,14 @@ struct GemmArgs {
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
 void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce
 void gemm_f64_partials(Exec& ex, const GemmArgs& g);  // partials only (no reduce)
-void gemm_f64_reduce(Exec& ex, const GemmArgs& g);    // reduce of the partials (bn = 128)
+void gemm_f64_reduce(Exec& ex, const GemmArgs& g);    // reduce of the partials
 void gemm_f32(Exec& ex, const GemmArgs& g);
 void gemm_f32_partials(Exec& ex, const GemmArgs& g);
 void gemm_ddf(Exec& ex, const GemmArgs& g);           // fl32(A)^T fl32(B) etc.
 // split-K plan: splits and kchunk for a long-K product with `tiles` output
 // tiles (kchunk_fixed > 0: fixed chunk length, for batches)
 void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int64_t kchunk_fixed = 0);
-int64_t gemm_tiles(int64_t M, int64_t N, int lower, int bn);
+int64_t gemm_tiles(int64_t M, int64_t N, int lower);
 
 // ---------------------------------------------------------------- TRSM / factorizations
 // Ap = A R^{-1}, R upper n x n (FP64), blocked substitution.
