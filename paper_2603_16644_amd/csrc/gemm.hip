@@ -75,7 +75,10 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     const TA* __restrict__ A = (const TA*)g.A;
     const TB* __restrict__ B = (const TB*)g.B;
     const double* __restrict__ bv = (const double*)g.bvec;
-    const bool fold = (bv != nullptr) && (tj == 0);
+    // op(A) bvec is formed by the work-groups of the diagonal tiles of a
+    // lower-triangle product (whose upper-right wavefront has no MFMA work)
+    // and otherwise by those of the first tile column
+    const bool fold = (bv != nullptr) && (g.lower ? ti == tj : tj == 0);
     // 16-byte vector loads when every run of APT (A) / BPT (B) elements is aligned
     const bool vecA = sizeof(TA) == 8 && ((g.lda & 1) == 0) && (((uintptr_t)A & 15) == 0);
     const bool vecB = sizeof(TB) == 8 && ((g.ldb & 1) == 0) && (((uintptr_t)B & 15) == 0);
