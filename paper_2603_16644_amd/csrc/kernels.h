@@ -36,6 +36,7 @@ inline int64_t opk_bytes(int op)
 struct SketchPlan {
     int op;
     int64_t chunk, nchunks, ldk, splits, kchunk;
+    int wide;       // 256 x 256 product tiles (one large unscaled sketch)
     size_t bytes;
 };
 // kchunk_fixed > 0: split the product over rows of A in chunks of this

@@ -364,6 +364,122 @@ __device__ void GemmLp<OP, SCALED>::run(const GemmLpArgs& a, int bx, int by)
     }
 }
 
+// Wide variant for one large unscaled sketch (BF16 or FP32 operands):
+// 256 x 256 output tile per work-group of eight waves (2 x 4 waves of
+// 128 x 64), K tiles of 128 bytes per row, two LDS buffers (one barrier per
+// K tile) and the next tile held in registers.  Twice the MFMA work of the
+// 128 x 128 tile per byte brought in from L2.
+constexpr int LW_BM = 256, LW_BN = 256;
+template <int OP>
+struct GemmLpW {
+    typedef GemmLpArgs Args;
+    static constexpr int NTH = 512, WPE = 2;
+    static __device__ void run(const GemmLpArgs& a, int bx, int by);
+};
+template <int OP>
+__device__ void GemmLpW<OP>::run(const GemmLpArgs& a, int bx, int by)
+{
+    typedef typename Op<OP>::T T;
+    const T* __restrict__ Om = (const T*)a.Om;
+    const T* __restrict__ Aq = (const T*)a.Aq;
+    const int64_t ldk = a.ldk, M = a.M, N = a.N, kchunk = a.kchunk;
+    float* __restrict__ P = a.P;
+    const int accumulate = a.accumulate;
+    constexpr int E = sizeof(T);
+    constexpr int BK = 128 / E;                  // K tile: 128 bytes per row
+    constexpr int PADE = 16 / E;
+    constexpr int LDR = BK + PADE;
+    constexpr int VPR = 8;                       // 16-byte vectors per tile row
+    constexpr int VPT = LW_BM * VPR / 512;       // vectors per thread per operand
+    __shared__ __attribute__((aligned(16))) T As[2][LW_BM * LDR];
+    __shared__ __attribute__((aligned(16))) T Bs[2][LW_BN * LDR];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w & 1, wn = w >> 1;
+    const int64_t tiles_m = (M + LW_BM - 1) / LW_BM;
+    const int64_t i0 = (int64_t)(bx % tiles_m) * LW_BM;
+    const int64_t j0 = (int64_t)(bx / tiles_m) * LW_BN;
+    const int64_t kbeg = (int64_t)by * kchunk;
+    const int64_t kend = (kbeg + kchunk < ldk) ? kbeg + kchunk : ldk;
+
+    v4f acc[8][4];
+#pragma unroll
+    for (int x = 0; x < 8; ++x)
+#pragma unroll
+        for (int y = 0; y < 4; ++y) acc[x][y] = (v4f){0.f, 0.f, 0.f, 0.f};
+
+    uint4 ra[VPT], rb[VPT];
+    auto gload = [&](int64_t k) {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + 512 * q;
+            const int row = v / VPR, c = v % VPR;
+            const int64_t gi = i0 + row, gj = j0 + row;
+            const int64_t koff = k + (int64_t)c * (16 / E);
+            ra[q] = (gi < M) ? *(const uint4*)(Om + gi * ldk + koff) : make_uint4(0, 0, 0, 0);
+            rb[q] = (gj < N) ? *(const uint4*)(Aq + gj * ldk + koff) : make_uint4(0, 0, 0, 0);
+        }
+    };
+    auto sstore = [&](int buf) {
+#pragma unroll
+        for (int q = 0; q < VPT; ++q) {
+            const int v = tid + 512 * q;
+            const int row = v / VPR, c = v % VPR;
+            *(uint4*)(As[buf] + row * LDR + c * (16 / E)) = ra[q];
+            *(uint4*)(Bs[buf] + row * LDR + c * (16 / E)) = rb[q];
+        }
+    };
+
+    const int r16 = lane & 15, g4 = lane >> 4;
+    int buf = 0;
+    if (kbeg < kend) {
+        gload(kbeg);
+        sstore(0);
+        if (kbeg + BK < kend) gload(kbeg + BK);
+    }
+    for (int64_t k = kbeg; k < kend; k += BK) {
+        __syncthreads();
+        const T* as = As[buf];
+        const T* bs = Bs[buf];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += Op<OP>::KI) {
+            const int ko = kk + g4 * Op<OP>::EPL;
+            const T* pa[4];
+            const T* pb[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) pb[t] = as + (wm * 128 + t * 16 + r16) * LDR + ko;   // Omega rows i
+#pragma unroll
+            for (int t = 0; t < 4; ++t) pa[t] = bs + (wn * 64 + t * 16 + r16) * LDR + ko;    // A columns j
+#pragma unroll
+            for (int ti = 0; ti < 8; ++ti)
+#pragma unroll
+                for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = mfma16<OP>(pa[tj], pb[ti], acc[ti][tj]);
+        }
+        if (k + BK < kend) {
+            sstore(buf ^ 1);
+            if (k + 2 * BK < kend) gload(k + 2 * BK);
+        }
+        buf ^= 1;
+    }
+    float* Pp = P + (int64_t)by * M * N;
+#pragma unroll
+    for (int ti = 0; ti < 8; ++ti) {
+        const int64_t i = i0 + wm * 128 + ti * 16 + r16;
+        if (i >= M) continue;
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t j = j0 + wn * 64 + tj * 16 + 4 * g4 + r;
+                if (j < N) {
+                    float v = acc[ti][tj][r];
+                    if (accumulate) v += Pp[i + j * M];
+                    Pp[i + j * M] = v;
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------- 4. reduction
 // As = scale * sum_split P[split]  (fixed order), written as FP32 and/or FP64.
 struct SketchReduceArgs {
@@ -425,6 +541,17 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br, in
         if (kc > p.ldk) kc = p.ldk;
         p.kchunk = kc;
         p.splits = ceil_div(p.ldk, kc);
+    } else if (op == OPK_BF16 || op == OPK_F32) {
+        // one wide-tile work-group per CU: the largest split count whose
+        // work-groups fit one wave of the machine
+        p.wide = 1;
+        const int64_t tiles = ceil_div(s, LW_BM) * ceil_div(n, LW_BN);
+        int64_t want = 256 / tiles;
+        int64_t maxsplit = p.ldk / (4 * align);
+        if (maxsplit < 1) maxsplit = 1;
+        p.splits = want < 1 ? 1 : (want < maxsplit ? want : maxsplit);
+        p.kchunk = ceil_div(ceil_div(p.ldk, p.splits), align) * align;
+        p.splits = ceil_div(p.ldk, p.kchunk);
     } else {
         // split-K so that tiles x splits fills the machine
         int64_t tiles = ceil_div(s, LP_BM) * ceil_div(n, LP_BN);
@@ -470,8 +597,15 @@ static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t
         if constexpr (SC) launch<QuantizeScaled<OP>>(ex, ceil_div(p.ldk, br), n, q);
         else launch<QuantizePlain<OP>>(ex, ceil_div(p.ldk, 256 * QUANT_PER), n, q);
         if (!ex.recording()) prof_mark(PH_SK_QUANT, ex.st);
-        launch<GemmLp<OP, SC>>(ex, ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits,
-                               GemmLpArgs{Omq, Aq, p.ldk, s, n, sc, br, (float*)P, p.kchunk, accumulate});
+        const GemmLpArgs ga{Omq, Aq, p.ldk, s, n, sc, br, (float*)P, p.kchunk, accumulate};
+        if constexpr (!SC) {
+            if (p.wide) {
+                launch<GemmLpW<OP>>(ex, ceil_div(s, LW_BM) * ceil_div(n, LW_BN), p.splits, ga);
+                if (!ex.recording()) prof_mark(PH_SK_GEMM, ex.st);
+                return;
+            }
+        }
+        launch<GemmLp<OP, SC>>(ex, ceil_div(s, LP_BM) * ceil_div(n, LP_BN), p.splits, ga);
     }
     if (!ex.recording()) prof_mark(PH_SK_GEMM, ex.st);
 }
