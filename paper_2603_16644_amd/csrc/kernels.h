@@ -111,20 +111,12 @@ size_t dinv_elems(int64_t n);
 template <typename T>
 void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int trans, int unit, T* Dinv,
                      int64_t block0 = 0, int64_t nblocks = -1);
-// x = U^{-1} L^{-1} P c (c and x may alias); DL, DU: block inverses of the
-// unit lower L and of U
-void lu_solve2(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
-               const double* DU, const double* c, double* x);
-// x = R^{-1} L^{-T} L^{-1} c (PNE: Cholesky factor L, preconditioner R) with
-// the block inverses DL of L and DR of R; Lt = L^T stored explicitly (n x n,
-// ld n) with the block inverses DLt of L^T, so that every solve reads its
-// matrix by columns
-void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
-                const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c,
-                double* x);
-// The same solves with one work-group per 64-row block and per-block flags
-// (flags: 3 * lb_flag_words(n) int32 for the PNE solve, 2 * ... for the LU
-// solve; any contents on entry).  c and x may alias.
+// x = R^{-1} L^{-T} L^{-1} c (PNE: Cholesky factor L, preconditioner R, with
+// L^T stored explicitly as Lt) and x = U^{-1} L^{-1} P c (HPNE: LU with unit
+// lower L), with the inverses DL, DLt, DR, DU of the 64 x 64 diagonal blocks;
+// one work-group per 64-row block and per-block flags (flags: 3 *
+// lb_flag_words(n) int32 for the PNE solve, 2 * ... for the LU solve; any
+// contents on entry).  c and x may alias.
 size_t lb_flag_words(int64_t n);
 void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                   const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,

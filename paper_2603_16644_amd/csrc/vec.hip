@@ -1,7 +1,8 @@
 // n-vector kernels of the solve and refinement steps (FP64 unless stated):
-// single-work-group triangular solves (trsv_dev.h), the residual r = b - A x,
-// the product y = X^T v split over rows with a fixed-order reduction, and
-// small helpers.
+// inverses of the 64 x 64 diagonal blocks (trsv_dev.h), triangular solves
+// with one work-group per 64-row block, the residual r = b - A x, the
+// product y = X^T v split over rows with a fixed-order reduction, and small
+// helpers.
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -9,7 +10,6 @@
 
 namespace pne {
 
-constexpr int TV_THREADS = 1024;
 constexpr int TV_MAXN = 4096;   // largest n of the solvers (vector held in LDS)
 
 size_t dinv_elems(int64_t n) { return (size_t)((n + TB - 1) / TB) * TB * TB; }
@@ -25,46 +25,6 @@ void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int
 }
 template void inv_diag_blocks<double>(Exec&, int64_t, const double*, int64_t, int, int, int, double*, int64_t, int64_t);
 template void inv_diag_blocks<float>(Exec&, int64_t, const float*, int64_t, int, int, int, float*, int64_t, int64_t);
-
-// PNE solve in one work-group: L z = c, L^T y = z, R x = y, with the inverted
-// diagonal blocks DL of L, DLt of L^T and DR of R.  L^T is read from its
-// explicit copy Lt so that all three matrices are read by columns
-// (contiguous across the threads of the update step).
-struct PneSolve3 {
-    struct Args {
-        int64_t n;
-        const double* L;
-        int64_t ldl;
-        const double* DL;
-        const double* Lt;
-        const double* DLt;
-        const double* R;
-        int64_t ldr;
-        const double* DR;
-        const double* c;
-        double* x;
-    };
-    static constexpr int NTH = TV_THREADS, WPE = 0;
-    static __device__ void run(const Args& a, int, int)
-    {
-        __shared__ double xs[TV_MAXN];
-        __shared__ double tmp[TB];
-        const int64_t n = a.n;
-        for (int64_t i = threadIdx.x; i < n; i += NTH) xs[i] = a.c[i];
-        __syncthreads();
-        wg_trsv_inv<double>(n, a.L, a.ldl, true, false, a.DL, false, xs, tmp);
-        wg_trsv_inv<double>(n, a.Lt, n, false, false, a.DLt, false, xs, tmp);
-        wg_trsv_inv<double>(n, a.R, a.ldr, false, false, a.DR, false, xs, tmp);
-        for (int64_t i = threadIdx.x; i < n; i += NTH) a.x[i] = xs[i];
-    }
-};
-
-void pne_solve3(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
-                const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c,
-                double* x)
-{
-    launch<PneSolve3>(ex, 1, 1, PneSolve3::Args{n, L, ldl, DL, Lt, DLt, R, ldr, DR, c, x});
-}
 
 // out(j, i) = in(i, j) through a 64 x 64 LDS tile per work-group.
 struct Transpose {
@@ -259,45 +219,6 @@ void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_
     launch<ApplyPivots>(ex, 1, 1, ApplyPivots::Args{n, piv, x});
     trsv_lb(ex, n, LU, ld, 1, DL, x, flags);
     trsv_lb(ex, n, LU, ld, 0, DU, x, flags + fw);
-}
-
-// HPNE solve: x = U^{-1} L^{-1} P c (row exchanges in order, unit lower L),
-// with the inverted diagonal blocks DL (unit lower) and DU (upper).
-struct LuSolve {
-    struct Args {
-        int64_t n;
-        const double* LU;
-        int64_t ld;
-        const int32_t* piv;
-        const double* DL;
-        const double* DU;
-        const double* c;
-        double* x;
-    };
-    static constexpr int NTH = TV_THREADS, WPE = 0;
-    static __device__ void run(const Args& a, int, int)
-    {
-        __shared__ double xs[TV_MAXN];
-        __shared__ double tmp[TB];
-        const int64_t n = a.n;
-        for (int64_t i = threadIdx.x; i < n; i += NTH) xs[i] = a.c[i];
-        __syncthreads();
-        if (threadIdx.x == 0)
-            for (int64_t k = 0; k < n; ++k) {
-                const int64_t p = a.piv[k];
-                if (p != k) { double t = xs[k]; xs[k] = xs[p]; xs[p] = t; }
-            }
-        __syncthreads();
-        wg_trsv_inv<double>(n, a.LU, a.ld, true, false, a.DL, false, xs, tmp);
-        wg_trsv_inv<double>(n, a.LU, a.ld, false, false, a.DU, false, xs, tmp);
-        for (int64_t i = threadIdx.x; i < n; i += NTH) a.x[i] = xs[i];
-    }
-};
-
-void lu_solve2(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
-               const double* DU, const double* c, double* x)
-{
-    launch<LuSolve>(ex, 1, 1, LuSolve::Args{n, LU, ld, piv, DL, DU, c, x});
 }
 
 // r = b - A x, one row per thread, x staged in LDS in chunks of 4096.
