@@ -69,7 +69,7 @@ size_t scratch_bytes(const Problem& p, int sk, int qr)
     size_t q = qr_workspace_bytes(p.s, p.n, qr);
     if (q > b) b = q;
     int64_t splits, kc;
-    plan_splitk(p.m, gemm_tiles(p.n, p.n, !p.hpne), &splits, &kc, p.kchunk_fixed);
+    plan_splitk(p.m, gemm_tiles(p.n, p.n, p.m, !p.hpne), &splits, &kc, p.kchunk_fixed);
     size_t g = ((size_t)splits * p.n * p.n + (size_t)splits * p.n) * sizeof(double) + 512;
     if (g > b) b = g;
     return b;
@@ -213,7 +213,7 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     // C = A_p^T A_p (PNE, lower tiles) or A_p^T A (HPNE); c = A_p^T b
     ex.stage(ST_GRAM);
     int64_t splits, kc;
-    const int64_t gtiles = gemm_tiles(n, n, !hpne);
+    const int64_t gtiles = gemm_tiles(n, n, m, !hpne);
     plan_splitk(m, gtiles, &splits, &kc, ex.kchunk_fixed);
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;

@@ -181,7 +181,7 @@ struct CePlan {
 static CePlan ce_plan(int64_t m, int64_t n, int64_t kchunk_fixed)
 {
     CePlan p;
-    plan_splitk(m, gemm_tiles(n, n, 1), &p.splits, &p.kchunk, kchunk_fixed);
+    plan_splitk(m, gemm_tiles(n, n, m, 1), &p.splits, &p.kchunk, kchunk_fixed);
     return p;
 }
 

@@ -327,21 +327,25 @@ __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
     }
 }
 
-// Output tile of a product: 128 x 128 in general; 128 x 64 for narrow
-// products (N <= 64); 64 x 64 for lower-triangle products of order <= 512,
-// where 128-wide tiles would spend a large share of their work on padding.
+// Output tile of a product.  Lower-triangle products: 64 x 64 up to order
+// 512 (128-wide tiles would spend a large share of their work on padding),
+// 128 x 128 above.  Other products: 64 x 64 when K is short (the tall
+// products of A R^-1, LU and Cholesky updates, where three work-groups per CU
+// and the finer grid beat the higher reuse of larger tiles), 128 x 128 (or
+// 128 x 64 for N <= 64) for long-K split products.
 struct TileShape {
     int bm, bn;
 };
-static TileShape tile_shape(int64_t, int64_t N, int lower)
+static TileShape tile_shape(int64_t, int64_t N, int64_t K, int lower)
 {
     if (lower) return N <= 512 ? TileShape{64, 64} : TileShape{128, 128};
+    if (K < 4096) return TileShape{64, 64};
     return N <= 64 ? TileShape{128, 64} : TileShape{128, 128};
 }
 
-int64_t gemm_tiles(int64_t M, int64_t N, int lower)
+int64_t gemm_tiles(int64_t M, int64_t N, int64_t K, int lower)
 {
-    const TileShape ts = tile_shape(M, N, lower);
+    const TileShape ts = tile_shape(M, N, K, lower);
     const int64_t tm = ceil_div(M, ts.bm), tn = ceil_div(N, ts.bn);
     if (lower) return tm * (tm + 1) / 2;  // square tiles, square problems
     return tm * tn;
@@ -383,7 +387,7 @@ void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int
 template <typename TC>
 static void gemm_reduce_launch(Exec& ex, const GemmArgs& g)
 {
-    const TileShape ts = tile_shape(g.M, g.N, g.lower);
+    const TileShape ts = tile_shape(g.M, g.N, g.K, g.lower);
     int64_t cnt = g.M * g.N;
     if (g.bvec && g.M > cnt) cnt = g.M;
     launch<GemmReduce<TC>>(ex, ceil_div(cnt, 256), 1, GemmReduceArgs{g, ts.bm, ts.bn});
@@ -401,8 +405,8 @@ template <typename TA, typename TB, typename TC>
 static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
 {
     GemmArgs g = g0;
-    const TileShape ts = tile_shape(g.M, g.N, g.lower);
-    const int64_t tiles = gemm_tiles(g.M, g.N, g.lower);
+    const TileShape ts = tile_shape(g.M, g.N, g.K, g.lower);
+    const int64_t tiles = gemm_tiles(g.M, g.N, g.K, g.lower);
     if (tiles == 0) return;
     const bool partial = g.splits > 1 || !reduce;
     if (!partial) {

@@ -78,7 +78,7 @@ void gemm_ddf(Exec& ex, const GemmArgs& g);           // fl32(A)^T fl32(B) etc.
 // split-K plan: splits and kchunk for a long-K product with `tiles` output
 // tiles (kchunk_fixed > 0: fixed chunk length, for batches)
 void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int64_t kchunk_fixed = 0);
-int64_t gemm_tiles(int64_t M, int64_t N, int lower);
+int64_t gemm_tiles(int64_t M, int64_t N, int64_t K, int lower);
 
 // ---------------------------------------------------------------- TRSM / factorizations
 // Ap = A R^{-1}, R upper n x n (FP64), blocked substitution.
