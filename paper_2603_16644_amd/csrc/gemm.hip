@@ -417,7 +417,9 @@ static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
     }
     if (g.splits < 1) g.splits = 1;
     if (g.kchunk <= 0) g.kchunk = ceil_div(ceil_div(g.K, g.splits), G_BK) * G_BK;
-    g.xcd_remap = !ex.recording() && g.splits > 1;
+    // (lower-triangle products only: on the FP64 sketch product, whose
+    // grid is several waves of work-groups, it made the launch slower)
+    g.xcd_remap = !ex.recording() && g.splits > 1 && g.lower;
     gemm_tiles_launch<TA, TB, TC, true>(ex, ts, tiles, g);
     if (reduce) gemm_reduce_launch<TC>(ex, g);
 }

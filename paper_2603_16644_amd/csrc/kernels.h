@@ -66,7 +66,7 @@ struct GemmArgs {
     int64_t splits, kchunk;
     void* P; int accumulate_partials;
     const void* bvec; void* Pc; void* cvec;
-    int xcd_remap;    // set by the launcher (direct split-K launches)
+    int xcd_remap;    // set by the launcher (direct split-K lower-triangle launches)
 };
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
 void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce
