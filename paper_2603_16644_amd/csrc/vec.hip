@@ -221,7 +221,12 @@ void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_
     trsv_lb(ex, n, LU, ld, 0, DU, x, flags + fw);
 }
 
-// r = b - A x, one row per thread, x staged in LDS in chunks of 4096.
+// r = b - A x.  A work-group takes 64 rows; its four wavefronts take the
+// columns j = q (mod 4), q = 0..3, so four times as many waves stream A as
+// with one row per thread, each lane with eight loads in flight; the four
+// partial sums of a row are added in q order.  x is staged in LDS in chunks
+// of 1024.
+constexpr int RES_ROWS = 64, RES_XCHUNK = 1024;
 struct Residual {
     struct Args {
         int64_t m, n;
@@ -234,33 +239,50 @@ struct Residual {
     static constexpr int NTH = 256, WPE = 0;
     static __device__ void run(const Args& a, int bx, int)
     {
-        __shared__ double xs[4096];
+        __shared__ double xs[RES_XCHUNK];
+        __shared__ double part[4][RES_ROWS];
         const int64_t m = a.m, n = a.n, lda = a.lda;
         const double* __restrict__ A = a.A;
-        const int64_t i = (int64_t)bx * 256 + threadIdx.x;
-        double acc = (i < m) ? a.b[i] : 0.0;
-        for (int64_t j0 = 0; j0 < n; j0 += 4096) {
-            const int64_t jw = (n - j0 < 4096) ? n - j0 : 4096;
+        const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
+        const int64_t i = (int64_t)bx * RES_ROWS + lane;
+        const bool in = i < m;
+        const double* __restrict__ Ai = A + (in ? i : 0);
+        double acc = 0.0;
+        for (int64_t j0 = 0; j0 < n; j0 += RES_XCHUNK) {
+            const int64_t jw = (n - j0 < RES_XCHUNK) ? n - j0 : RES_XCHUNK;
             __syncthreads();
-            for (int64_t j = threadIdx.x; j < jw; j += 256) xs[j] = a.x[j0 + j];
+            for (int64_t j = threadIdx.x; j < jw; j += NTH) xs[j] = a.x[j0 + j];
             __syncthreads();
-            if (i < m)
-                for (int64_t j = 0; j < jw; ++j) acc -= A[i + (j0 + j) * lda] * xs[j];
+            if (in) {
+                int64_t j = q;
+                for (; j + 28 < jw; j += 32) {
+                    double v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) v[u] = Ai[(j0 + j + 4 * u) * lda];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) acc = fma(v[u], xs[j + 4 * u], acc);
+                }
+                for (; j < jw; j += 4) acc = fma(Ai[(j0 + j) * lda], xs[j], acc);
+            }
         }
-        if (i < m) a.r[i] = acc;
+        part[q][lane] = acc;
+        __syncthreads();
+        if (q == 0 && in) a.r[i] = a.b[i] - (((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane]);
     }
 };
 
 void residual(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* b, const double* x,
               double* r)
 {
-    launch<Residual>(ex, ceil_div(m, 256), 1, Residual::Args{m, n, A, lda, b, x, r});
+    launch<Residual>(ex, ceil_div(m, RES_ROWS), 1, Residual::Args{m, n, A, lda, b, x, r});
 }
 
-// y = X^T v: work-group (column j, row chunk z) -> P[z * n + j]; then reduce.
+// y = X^T v: work-group (four columns from j, row chunk z) -> P[z * n + j..];
+// then a fixed-order reduction over the chunks.
 constexpr int64_t GV_CHUNK = 16384;
 size_t gemv_t_partials(int64_t m, int64_t n) { return (size_t)ceil_div(m, GV_CHUNK) * n; }
 
+constexpr int GV_COLS = 4;   // columns per work-group (v read once for all four)
 struct GemvT {
     struct Args {
         int64_t m, n;
@@ -272,15 +294,34 @@ struct GemvT {
     static constexpr int NTH = 256, WPE = 0;
     static __device__ void run(const Args& a, int bx, int by)
     {
-        __shared__ double red[4];
-        const int64_t j = bx, z = by, m = a.m;
+        __shared__ double red[GV_COLS][4];
+        const int64_t jb = (int64_t)bx * GV_COLS, z = by, m = a.m, n = a.n, ldx = a.ldx;
         const int64_t k0 = z * GV_CHUNK, k1 = (k0 + GV_CHUNK < m) ? k0 + GV_CHUNK : m;
         const double* __restrict__ X = a.X;
         const double* __restrict__ v = a.v;
-        double s = 0.0;
-        for (int64_t k = k0 + threadIdx.x; k < k1; k += 256) s += X[k + j * a.ldx] * v[k];
-        s = block_sum(s, red);
-        if (threadIdx.x == 0) a.P[z * a.n + j] = s;
+        double s[GV_COLS];
+        const double* Xc[GV_COLS];
+#pragma unroll
+        for (int c = 0; c < GV_COLS; ++c) {
+            s[c] = 0.0;
+            Xc[c] = X + ((jb + c < n) ? jb + c : jb) * ldx;
+        }
+        for (int64_t k = k0 + threadIdx.x; k < k1; k += NTH) {
+            const double vk = v[k];
+#pragma unroll
+            for (int c = 0; c < GV_COLS; ++c) s[c] += Xc[c][k] * vk;
+        }
+        const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+        for (int c = 0; c < GV_COLS; ++c) {
+            const double t = wave_sum(s[c]);
+            if (lane == 0) red[c][w] = t;
+        }
+        __syncthreads();
+        if (threadIdx.x < GV_COLS && jb + threadIdx.x < n) {
+            const int c = threadIdx.x;
+            a.P[z * n + jb + c] = ((red[c][0] + red[c][1]) + red[c][2]) + red[c][3];
+        }
     }
 };
 
@@ -305,7 +346,7 @@ void gemv_t(Exec& ex, int64_t m, int64_t n, const double* X, int64_t ldx, const 
             double* P)
 {
     const int64_t splits = ceil_div(m, GV_CHUNK);
-    launch<GemvT>(ex, n, splits, GemvT::Args{m, n, X, ldx, v, P});
+    launch<GemvT>(ex, ceil_div(n, GV_COLS), splits, GemvT::Args{m, n, X, ldx, v, P});
     launch<GemvTReduce>(ex, ceil_div(n, 256), 1, GemvTReduce::Args{n, splits, P, y});
 }
 
