@@ -574,14 +574,55 @@ SketchPlan plan_sketch(int64_t m, int64_t n, int64_t s, int prec, int64_t br, in
     return p;
 }
 
+// Generation of Omega (arithmetic-bound) and conversion of A (memory-bound)
+// in one launch, their work-groups interleaved in proportion to their
+// counts so that the two run side by side: work-group b is Omega work-group
+// floor(b * G_o / G) when that index steps at b, otherwise conversion
+// work-group b - floor(b * G_o / G).
+struct SketchPrepArgs {
+    OmegaArgs o;
+    QuantArgs q;
+    int64_t ogx, ogn, qgx, total;
+};
+template <int OP>
+struct SketchPrep {
+    typedef SketchPrepArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const SketchPrepArgs& a, int bx, int)
+    {
+        const int64_t b = bx;
+        const int64_t oi = b * a.ogn / a.total, oi1 = (b + 1) * a.ogn / a.total;
+        if (oi1 > oi) {
+            OmegaGen<OP>::run(a.o, (int)(oi % a.ogx), (int)(oi / a.ogx));
+        } else {
+            const int64_t qi = b - oi;
+            QuantizePlain<OP>::run(a.q, (int)(qi % a.qgx), (int)(qi / a.qgx));
+        }
+    }
+};
+
 template <int OP>
 static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t lda, int64_t k0,
                          int64_t kc, int64_t n, int64_t s, uint64_t seed, uint32_t pid, int64_t br,
                          void* Omq, void* Aq, float* sc, void* P, int accumulate)
 {
-    launch<OmegaGen<OP>>(ex, ceil_div(p.ldk, 256), ceil_div(ceil_div(s, 4), OMEGA_QUADS),
-                         OmegaArgs{seed, pid, s, k0, kc, p.ldk, Omq});
-    if (!ex.recording()) prof_mark(PH_SK_OMEGA, ex.st);
+    const OmegaArgs oa{seed, pid, s, k0, kc, p.ldk, Omq};
+    const int64_t ogx = ceil_div(p.ldk, 256), ogy = ceil_div(ceil_div(s, 4), OMEGA_QUADS);
+    constexpr bool SC = (OP == OPK_FP8 || OP == OPK_F16);
+    if constexpr (OP != OPK_F64 && !SC) {
+        // Omega and the conversion of A in one launch
+        const QuantArgs q{A, lda, k0, kc, p.ldk, br, n, Aq, sc};
+        const int64_t qgx = ceil_div(p.ldk, 256 * QUANT_PER);
+        const int64_t ogn = ogx * ogy, total = ogn + qgx * n;
+        launch<SketchPrep<OP>>(ex, total, 1, SketchPrepArgs{oa, q, ogx, ogn, qgx, total});
+        if (!ex.recording()) {
+            prof_mark(PH_SK_OMEGA, ex.st);
+            prof_mark(PH_SK_QUANT, ex.st);
+        }
+    } else {
+        launch<OmegaGen<OP>>(ex, ogx, ogy, oa);
+        if (!ex.recording()) prof_mark(PH_SK_OMEGA, ex.st);
+    }
     if constexpr (OP == OPK_F64) {
         // C(s x n) = Omega_q (rows contiguous over k) * A(chunk rows)
         GemmArgs g{};
@@ -592,11 +633,11 @@ static void launch_chunk(Exec& ex, const SketchPlan& p, const double* A, int64_t
         g.P = (double*)P; g.accumulate_partials = accumulate;
         gemm_f64_partials(ex, g);
     } else {
-        constexpr bool SC = (OP == OPK_FP8 || OP == OPK_F16);
-        const QuantArgs q{A, lda, k0, kc, p.ldk, br, n, Aq, sc};
-        if constexpr (SC) launch<QuantizeScaled<OP>>(ex, ceil_div(p.ldk, br), n, q);
-        else launch<QuantizePlain<OP>>(ex, ceil_div(p.ldk, 256 * QUANT_PER), n, q);
-        if (!ex.recording()) prof_mark(PH_SK_QUANT, ex.st);
+        if constexpr (SC) {
+            const QuantArgs q{A, lda, k0, kc, p.ldk, br, n, Aq, sc};
+            launch<QuantizeScaled<OP>>(ex, ceil_div(p.ldk, br), n, q);
+            if (!ex.recording()) prof_mark(PH_SK_QUANT, ex.st);
+        }
         const GemmLpArgs ga{Omq, Aq, p.ldk, s, n, sc, br, (float*)P, p.kchunk, accumulate};
         if constexpr (!SC) {
             if (p.wide) {
