@@ -52,6 +52,7 @@ struct Buffers {
     int32_t* piv;       // n
     double* y;          // n
     double* d;          // n
+    double* t;          // n (intermediate vector of the chained solves)
     double* r;          // m
     double* gv;         // gemv partials
     double* dinv1;      // block inverses: Cholesky factor L, or unit lower L of the LU
@@ -105,6 +106,7 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
     b.piv = ar.take<int32_t>(p.n);
     b.y = ar.take<double>(p.n);
     b.d = ar.take<double>(p.n);
+    b.t = ar.take<double>(p.n);
     b.r = ar.take<double>(p.m);
     b.gv = ar.take<double>(gemv_t_partials(p.m, p.n));
     b.dinv1 = ar.take<double>(dinv_elems(p.n));
@@ -246,7 +248,7 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     mark(ex, PH_FACTOR);
     ex.stage(ST_SOLVE);
     if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, b.flags);
-    else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx, b.flags);
+    else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx, b.t, b.flags);
     mark(ex, PH_SOLVE);
     ex.stage(ST_REFINE);
     for (int k = 0; k < p.refine; ++k) {
@@ -254,7 +256,7 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
         residual(ex, m, n, dA, lda, db, dx, b.r);
         gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
         if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, b.flags);
-        else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.flags);
+        else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.t, b.flags);
         axpy_update(ex, n, dx, b.d);
     }
     ex.stage(ST_FINISH);

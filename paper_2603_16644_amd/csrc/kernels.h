@@ -121,7 +121,7 @@ void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int
 size_t lb_flag_words(int64_t n);
 void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                   const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
-                  int32_t* flags);
+                  double* y, int32_t* flags);   // y: n-vector scratch (L^T y = z)
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
                  const double* DU, const double* c, double* x, int32_t* flags);
 // out (c x r, ldo) = in^T (in r x c, ldi)

@@ -91,6 +91,89 @@ __device__ __forceinline__ void lb_wait(int32_t* f)
     }
 }
 
+// One triangular solve of the chain: U x = rhs (rhs == x: in place).  With
+// rhs_flags set, the right-hand side block b is the output of another solve
+// of the same launch and is read once that solve has raised rhs_flags[1 + b].
+struct LBSolve {
+    int64_t n;
+    const double* M;
+    int64_t ld;
+    int lower;
+    const double* D;
+    const double* rhs;
+    double* x;
+    int32_t* flags;            // flags[1 + b]: block b of x is final
+    const int32_t* rhs_flags;  // null, or the flags of the solve that writes rhs
+};
+
+// Work-group of the t-th block (in dependency order) of solve sv.
+__device__ void lb_solve_block(const LBSolve& sv, int64_t t)
+{
+    __shared__ double xs[TB];
+    __shared__ double red[4][TB];
+    __shared__ double vb[TB];
+    const int tid = threadIdx.x, i = tid & 63, p = tid >> 6;
+    const int64_t n = sv.n, nb = (n + TB - 1) / TB;
+    const int64_t b = sv.lower ? t : nb - 1 - t;
+    const int64_t r0 = b * TB;
+    const int bw = (int)((n - r0 < TB) ? n - r0 : TB);
+    const double* __restrict__ M = sv.M;
+    double s = 0.0;
+    for (int64_t q = 0; q < t; ++q) {
+        const int64_t j = sv.lower ? q : nb - 1 - q;
+        const int64_t c0 = j * TB;
+        const int jw = (int)((n - c0 < TB) ? n - c0 : TB);
+        if (tid == 0) lb_wait(sv.flags + 1 + j);
+        __syncthreads();
+        if (tid < TB)
+            xs[tid] = (tid < jw) ? __hip_atomic_load(sv.x + c0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                 : 0.0;
+        __syncthreads();
+        if (i < bw) {
+            double mv[16];
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) {
+                const int k = 16 * p + kk;
+                mv[kk] = (k < jw) ? M[(r0 + i) + (c0 + k) * sv.ld] : 0.0;
+            }
+#pragma unroll
+            for (int kk = 0; kk < 16; ++kk) s += mv[kk] * xs[16 * p + kk];
+        }
+        __syncthreads();
+    }
+    red[p][i] = s;
+    if (sv.rhs_flags && tid == 0) lb_wait(const_cast<int32_t*>(sv.rhs_flags) + 1 + b);
+    __syncthreads();
+    if (tid < TB) {
+        double rv = 0.0;
+        if (tid < bw)
+            rv = sv.rhs_flags ? __hip_atomic_load(sv.rhs + r0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                              : sv.rhs[r0 + tid];
+        vb[tid] = (tid < bw) ? rv - (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) : 0.0;
+    }
+    __syncthreads();
+    const double* Db = sv.D + b * TB * TB;
+    double u = 0.0;
+    {
+        double dv[16];
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) {
+            const int k = 16 * p + kk;
+            dv[kk] = (k < bw && i < bw) ? Db[i + k * TB] : 0.0;
+        }
+#pragma unroll
+        for (int kk = 0; kk < 16; ++kk) u += dv[kk] * vb[16 * p + kk];
+    }
+    red[p][i] = u;
+    __syncthreads();
+    if (tid < bw) {
+        sv.x[r0 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+        __threadfence();
+    }
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(sv.flags + 1 + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct TrsvLB {
     struct Args {
         int64_t n;
@@ -105,65 +188,30 @@ struct TrsvLB {
     static __device__ void run(const Args& a, int, int)
     {
         __shared__ int32_t tk;
-        __shared__ double xs[TB];
-        __shared__ double red[4][TB];
-        __shared__ double vb[TB];
-        const int tid = threadIdx.x, i = tid & 63, p = tid >> 6;
-        const int64_t n = a.n, nb = (n + TB - 1) / TB;
-        if (tid == 0) tk = atomicAdd(a.flags, 1);
+        if (threadIdx.x == 0) tk = atomicAdd(a.flags, 1);
+        __syncthreads();
+        lb_solve_block(LBSolve{a.n, a.M, a.ld, a.lower, a.D, a.x, a.x, a.flags, nullptr}, tk);
+    }
+};
+
+// Two chained solves in the same direction in one launch: U1 y = c, then
+// U2 x = y.  Tickets alternate between them (2k: step k of the first, 2k+1:
+// step k of the second), so the second follows one block behind the first
+// and every block waits only for blocks holding smaller tickets.
+struct TrsvLB2 {
+    struct Args {
+        LBSolve s1, s2;     // s2.rhs = s1.x, s2.rhs_flags = s1.flags
+        int32_t* ticket;    // zero at launch
+    };
+    static constexpr int NTH = LB_THREADS, WPE = 0;
+    static __device__ void run(const Args& a, int, int)
+    {
+        __shared__ int32_t tk;
+        if (threadIdx.x == 0) tk = atomicAdd(a.ticket, 1);
         __syncthreads();
         const int64_t t = tk;
-        const int64_t b = a.lower ? t : nb - 1 - t;
-        const int64_t r0 = b * TB;
-        const int bw = (int)((n - r0 < TB) ? n - r0 : TB);
-        const double* __restrict__ M = a.M;
-        double s = 0.0;
-        for (int64_t q = 0; q < t; ++q) {
-            const int64_t j = a.lower ? q : nb - 1 - q;
-            const int64_t c0 = j * TB;
-            const int jw = (int)((n - c0 < TB) ? n - c0 : TB);
-            if (tid == 0) lb_wait(a.flags + 1 + j);
-            __syncthreads();
-            if (tid < TB)
-                xs[tid] = (tid < jw) ? __hip_atomic_load(a.x + c0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                     : 0.0;
-            __syncthreads();
-            if (i < bw) {
-                double mv[16];
-#pragma unroll
-                for (int kk = 0; kk < 16; ++kk) {
-                    const int k = 16 * p + kk;
-                    mv[kk] = (k < jw) ? M[(r0 + i) + (c0 + k) * a.ld] : 0.0;
-                }
-#pragma unroll
-                for (int kk = 0; kk < 16; ++kk) s += mv[kk] * xs[16 * p + kk];
-            }
-            __syncthreads();
-        }
-        red[p][i] = s;
-        __syncthreads();
-        if (tid < TB) vb[tid] = (tid < bw) ? a.x[r0 + tid] - (((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid]) : 0.0;
-        __syncthreads();
-        const double* Db = a.D + b * TB * TB;
-        double u = 0.0;
-        {
-            double dv[16];
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) {
-                const int k = 16 * p + kk;
-                dv[kk] = (k < bw && i < bw) ? Db[i + k * TB] : 0.0;
-            }
-#pragma unroll
-            for (int kk = 0; kk < 16; ++kk) u += dv[kk] * vb[16 * p + kk];
-        }
-        red[p][i] = u;
-        __syncthreads();
-        if (tid < bw) {
-            a.x[r0 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
-            __threadfence();
-        }
-        __syncthreads();
-        if (tid == 0) __hip_atomic_store(a.flags + 1 + b, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        if ((t & 1) == 0) lb_solve_block(a.s1, t >> 1);
+        else lb_solve_block(a.s2, t >> 1);
     }
 };
 
@@ -200,14 +248,17 @@ struct ApplyPivots {
 
 void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                   const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
-                  int32_t* flags)
+                  double* y, int32_t* flags)
 {
     const int64_t fw = (int64_t)lb_flag_words(n);
     zero_i32(ex, 3 * fw, flags);
     if (c != x) copy_f64(ex, n, 1, c, n, x, n);
     trsv_lb(ex, n, L, ldl, 1, DL, x, flags);
-    trsv_lb(ex, n, Lt, n, 0, DLt, x, flags + fw);
-    trsv_lb(ex, n, R, ldr, 0, DR, x, flags + 2 * fw);
+    // L^T y = z into y, then R x = y, in one launch (both backward)
+    const LBSolve s1{n, Lt, n, 0, DLt, x, y, flags + fw, nullptr};
+    const LBSolve s2{n, R, ldr, 0, DR, y, x, flags + 2 * fw, flags + fw};
+    const int64_t nb = (n + TB - 1) / TB;
+    launch<TrsvLB2>(ex, 2 * nb, 1, TrsvLB2::Args{s1, s2, flags + fw});
 }
 
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
