@@ -327,19 +327,19 @@ __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
     }
 }
 
-// Output tile of a product.  Lower-triangle products: 64 x 64 up to order
-// 512 (128-wide tiles would spend a large share of their work on padding),
-// 128 x 128 above.  Other products: 64 x 64 when K is short (the tall
-// products of A R^-1, LU and Cholesky updates, where three work-groups per CU
-// and the finer grid beat the higher reuse of larger tiles), 128 x 128 (or
-// 128 x 64 for N <= 64) for long-K split products.
+// Output tile of a product.  64 x 64 when K is short (the tall products of
+// A R^-1, the Cholesky and LU updates: three work-groups per CU and the finer
+// grid beat the higher reuse of larger tiles).  Long-K products: lower
+// triangles 64 x 64 up to order 512 (128-wide tiles would spend a large
+// share of their work on padding) and 128 x 128 above; others 128 x 128, or
+// 128 x 64 for N <= 64.
 struct TileShape {
     int bm, bn;
 };
 static TileShape tile_shape(int64_t, int64_t N, int64_t K, int lower)
 {
-    if (lower) return N <= 512 ? TileShape{64, 64} : TileShape{128, 128};
     if (K < 4096) return TileShape{64, 64};
+    if (lower) return N <= 512 ? TileShape{64, 64} : TileShape{128, 128};
     return N <= 64 ? TileShape{128, 64} : TileShape{128, 128};
 }
 
