@@ -63,6 +63,7 @@ def lib():
             "oracle_upper_solve": (i32, [i64, P, i64, P, P]),
             "oracle_cond_est": (i32, [i64, i64, P, i64, ctypes.c_double, P, P, P]),
             "oracle_sketch_entries": (i32, [i64, P, i64, i64, u64, u32, i32, i64, i64, P, P, P, P]),
+            "oracle_fp16_qr_scale": (ctypes.c_double, [i64, i64, P, i64]),
             "oracle_solve": (i32, [i32, i64, i64, P, i64, P, i64, u64, u32, i32, i32, i64, i32,
                                    ctypes.c_double, P, P, P, P]),
         }
@@ -131,6 +132,13 @@ def sketch_entries(A, s: int, seed: int, rows, cols, prec: str = "fp64", pid: in
     if rc:
         raise ValueError(f"oracle_sketch_entries failed: {rc}")
     return out, out_abs
+
+
+def fp16_qr_scale(As) -> float:
+    """Power-of-two factor applied to a sketch before its FP16 QR."""
+    As = _f64(As)
+    s, n = As.shape
+    return float(lib().oracle_fp16_qr_scale(s, n, _ptr(As), s))
 
 
 def householder_r(W) -> np.ndarray:

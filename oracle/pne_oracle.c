@@ -141,7 +141,7 @@ static double to_operand(double x, int prec)
 }
 
 /* ------------------------------------------------------------------------
- * Sketch A_s = Omega A (Algorithm 1, "Sketch"; Section 5.2, randomized
+ * Sketch A_s = Omega A (Algorithm 1, "Sketch"; Section 6.2, randomized
  * preconditioner), Omega Gaussian with N(0,1/s) entries.
  *
  * Operand rounding per precision (the definition the GPU implements):
@@ -281,11 +281,11 @@ int oracle_householder_r(int64_t s, int64_t n, double* W, int64_t ldw, double* R
 }
 
 /* Back substitution R x = y, R upper triangular n x n.  Returns 1000+k if
- * R(k,k) == 0 (1-based k); x is then left as NaN. */
+ * R(k,k) is zero or not finite (1-based k); x is then left as NaN. */
 static int solve_upper(int64_t n, const double* R, int64_t ldr, const double* y, double* x)
 {
     for (int64_t k = 0; k < n; ++k)
-        if (R[IDX(k, k, ldr)] == 0.0) {
+        if (R[IDX(k, k, ldr)] == 0.0 || !isfinite(R[IDX(k, k, ldr)])) {
             for (int64_t i = 0; i < n; ++i) x[i] = NAN;
             return 1000 + (int)k + 1;
         }
@@ -299,7 +299,7 @@ static int solve_upper(int64_t n, const double* R, int64_t ldr, const double* y,
 
 /* ------------------------------------------------------------------------
  * Least squares by Householder QR (the role of the direct QR solver the paper
- * compares against, Section 6.4; Golub & Van Loan Algorithm 5.3.2): reflect A
+ * compares against, Section 7.4; Golub & Van Loan Algorithm 5.3.2): reflect A
  * to upper triangular form, apply the same reflectors to b, back-substitute
  * R x = (Q^T b)(1:n).  This is the accuracy yardstick of every solve.
  * ---------------------------------------------------------------------- */
@@ -344,7 +344,7 @@ int oracle_precondition(int64_t m, int64_t n, const double* A, int64_t lda, cons
                         int64_t ldr, double* Ap, int64_t ldap)
 {
     for (int64_t k = 0; k < n; ++k)
-        if (R[IDX(k, k, ldr)] == 0.0) return 1000 + (int)k + 1;
+        if (R[IDX(k, k, ldr)] == 0.0 || !isfinite(R[IDX(k, k, ldr)])) return 1000 + (int)k + 1;
     for (int64_t i = 0; i < m; ++i)
         for (int64_t j = 0; j < n; ++j) {
             double acc = A[IDX(i, j, lda)];
@@ -396,18 +396,23 @@ int oracle_cholesky(int64_t n, double* C, int64_t ldc)
     return 0;
 }
 
+/* Magnitude used by the pivot search: |x|, with NaN counted as +inf so that a
+ * column holding a NaN selects a non-finite pivot (and reports a breakdown)
+ * instead of silently passing over it. */
+static double pivot_mag(double x) { return isnan(x) ? INFINITY : fabs(x); }
+
 /* LU with partial pivoting P C = L U (Golub & Van Loan Algorithm 3.4.1):
  * at column k the pivot is the first row of largest absolute value in
  * C(k:n-1, k).  piv[k] = row swapped with k (0-based).  Returns 3000+k if the
- * pivot is zero. */
+ * pivot is zero or not finite (the elimination of that column is skipped). */
 int oracle_lu(int64_t n, double* C, int64_t ldc, int32_t* piv)
 {
     int info = 0;
     for (int64_t k = 0; k < n; ++k) {
         int64_t p = k;
-        double best = fabs(C[IDX(k, k, ldc)]);
+        double best = pivot_mag(C[IDX(k, k, ldc)]);
         for (int64_t i = k + 1; i < n; ++i)
-            if (fabs(C[IDX(i, k, ldc)]) > best) { best = fabs(C[IDX(i, k, ldc)]); p = i; }
+            if (pivot_mag(C[IDX(i, k, ldc)]) > best) { best = pivot_mag(C[IDX(i, k, ldc)]); p = i; }
         piv[k] = (int32_t)p;
         if (p != k)
             for (int64_t j = 0; j < n; ++j) {
@@ -416,7 +421,7 @@ int oracle_lu(int64_t n, double* C, int64_t ldc, int32_t* piv)
                 C[IDX(p, j, ldc)] = t;
             }
         double pv = C[IDX(k, k, ldc)];
-        if (pv == 0.0) { if (!info) info = 3000 + (int)k + 1; continue; }
+        if (pv == 0.0 || !isfinite(pv)) { if (!info) info = 3000 + (int)k + 1; continue; }
         for (int64_t i = k + 1; i < n; ++i) C[IDX(i, k, ldc)] /= pv;
         for (int64_t j = k + 1; j < n; ++j)
             for (int64_t i = k + 1; i < n; ++i)
@@ -465,7 +470,7 @@ static void lu_solve(int64_t n, const double* LU, int64_t ldlu, const int32_t* p
 }
 
 /* ------------------------------------------------------------------------
- * Condition estimate in single precision (Section 5.1, Algorithm 1 first step).
+ * Condition estimate in single precision (Section 6.1, Algorithm 1 first step).
  *   G = fl32(A)^T fl32(A) summed in FP32; FP32 Cholesky G = L L^T (any
  *   non-positive or non-finite pivot => the estimate "overflows");
  *   est ~ ||G^{-1}||_1 by Hager's method (W. W. Hager, "Condition estimates",
@@ -480,7 +485,7 @@ static void lu_solve(int64_t n, const double* LU, int64_t ldlu, const int32_t* p
  * else FP64 (also when the estimate overflows).  known_kappa > 0 skips the
  * estimate and applies the same thresholds to log10(known_kappa).
  * Parity unpinned for the exact kappa0 value beyond the Hager lower-bound
- * property; the precision picks are pinned by the worked cases of Section 6.4.
+ * property; the precision picks are pinned by the worked cases of Section 7.4.
  * ---------------------------------------------------------------------- */
 static int pick_precision(float kappa0)
 {
@@ -585,6 +590,31 @@ int oracle_cond_est(int64_t m, int64_t n, const double* A, int64_t lda, double k
     return 0;
 }
 
+/* Power-of-two factor applied to the s x n sketch before it is rounded to
+ * FP16 for the QR: with amax = max |fl32(A_s)| = f 2^E (f in [1/2, 1)) and
+ * t the smallest integer with 4^t >= s, the factor is 2^(14 - t - E).  Then
+ * every entry of the scaled sketch is below 2^14 / sqrt(s), every column
+ * 2-norm (and so every entry of R_s) below 2^14, inside the FP16 range
+ * (largest finite value 65504).  Returns 1 for an all-zero or non-finite
+ * sketch.  (Library reading: the paper fixes no scaling for the half
+ * precision QR.) */
+double oracle_fp16_qr_scale(int64_t s, int64_t n, const double* As, int64_t ldas)
+{
+    double amax = 0.0;
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t i = 0; i < s; ++i) {
+            double v = fabs(oracle_round_fp32(As[IDX(i, j, ldas)]));
+            if (!isfinite(v)) return 1.0;
+            if (v > amax) amax = v;
+        }
+    if (amax == 0.0) return 1.0;
+    int t = 0;
+    while (t < 31 && ((int64_t)1 << (2 * t)) < s) ++t;
+    int E;
+    frexp(amax, &E);
+    return ldexp(1.0, 14 - t - E);
+}
+
 /* ------------------------------------------------------------------------
  * PNE / HPNE with a randomized preconditioner (Algorithm 1; PNE: the
  * preconditioned normal equations A_p^T A_p y = A_p^T b, R_s x = y; HPNE:
@@ -612,6 +642,7 @@ int oracle_solve(int hpne, int64_t m, int64_t n, const double* A, int64_t lda, c
 {
     if (m < n || n < 1 || lda < m || s < n) return -1;
     float kappa0 = NAN;
+    double qscale = 1.0;
     if (sketch_prec == PREC_AUTO || qr_prec == PREC_AUTO) {
         int32_t choice;
         oracle_cond_est(m, n, A, lda, known_kappa, &kappa0, NULL, &choice);
@@ -636,12 +667,18 @@ int oracle_solve(int hpne, int64_t m, int64_t n, const double* A, int64_t lda, c
 
     info = oracle_sketch(m, n, A, lda, s, seed, pid, sketch_prec, block_rows, As, s, NULL);
     if (info) goto done;
+    /* FP16 has a narrow exponent range: the sketch is scaled by a power of
+     * two before the rounding and R_s unscaled after it (exact), so that the
+     * precision choice depends on the conditioning only, not on the scale of
+     * A (Algorithm 1 picks u_p from kappa alone). */
+    qscale = (qr_prec == PREC_FP16) ? oracle_fp16_qr_scale(s, n, As, s) : 1.0;
     if (qr_prec != PREC_FP64)
-        for (size_t i = 0; i < (size_t)s * (size_t)n; ++i) As[i] = to_operand(As[i], qr_prec);
+        for (size_t i = 0; i < (size_t)s * (size_t)n; ++i)
+            As[i] = to_operand(oracle_round_fp32(As[i]) * qscale, qr_prec);
     info = oracle_householder_r(s, n, As, s, R, n);
     if (info) goto done;
     if (qr_prec != PREC_FP64)
-        for (size_t i = 0; i < nn; ++i) R[i] = to_operand(R[i], qr_prec);
+        for (size_t i = 0; i < nn; ++i) R[i] = to_operand(R[i], qr_prec) / qscale;
     if (R_out) memcpy(R_out, R, sizeof(double) * nn);
 
     info = oracle_precondition(m, n, A, lda, R, n, Ap, m);

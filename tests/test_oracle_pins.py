@@ -128,6 +128,70 @@ def test_sketch_block_scaled(orc, prec):
     np.testing.assert_allclose(got, ref, rtol=1e-12, atol=1e-300)
 
 
+def _lib_round(M, prec):
+    """Library conversion of float64 values through FP32 to the operand format."""
+    t = torch.tensor(np.asarray(M, dtype=np.float64).astype(np.float32))
+    if prec == "fp64":
+        return torch.tensor(np.asarray(M, dtype=np.float64))
+    if prec == "fp32":
+        return t.to(torch.float64)
+    if prec == "bf16":
+        return t.to(torch.bfloat16).to(torch.float64)
+    if prec == "fp16":
+        return t.to(torch.float16).to(torch.float64)
+    return t.clamp(-448, 448).to(torch.float8_e4m3fn).to(torch.float64)
+
+
+def _explicit_sketch(orc, A, s, seed, prec, br=128):
+    """Omega A / sqrt(s) and |Omega_q| |A_q| scale / sqrt(s) with the oracle's
+    Omega, operands rounded by the torch conversions and the per-block scales
+    of the FP16/FP8 formats formed here."""
+    m, n = A.shape
+    Om = orc.omega(seed=seed, s=s, m=m)
+    Oq = _lib_round(Om, prec)
+    if prec not in ("fp16", "fp8"):
+        Aq = _lib_round(A, prec)
+        return ((Oq @ Aq) / math.sqrt(s)).numpy(), ((Oq.abs() @ Aq.abs()) / math.sqrt(s)).numpy()
+    A32 = torch.tensor(A.astype(np.float32))
+    ref = torch.zeros(s, n, dtype=torch.float64)
+    ab = torch.zeros(s, n, dtype=torch.float64)
+    for k0 in range(0, m, br):
+        blk = A32[k0:k0 + br]
+        amax = blk.abs().max(dim=0).values
+        if prec == "fp16":
+            e = torch.floor(torch.log2(amax.double()))
+            scale = torch.where(amax > 0, 2.0 ** (e - 14), torch.zeros_like(e)).float()
+        else:
+            scale = torch.where(amax > 0, amax / 448.0, torch.zeros_like(amax))
+        safe = torch.where(scale > 0, scale, torch.ones_like(scale))
+        t = blk / safe
+        q = t.to(torch.float16) if prec == "fp16" else t.clamp(-448, 448).to(torch.float8_e4m3fn)
+        q = torch.where(scale > 0, q.to(torch.float64), torch.zeros(q.shape, dtype=torch.float64))
+        ref += (Oq[:, k0:k0 + br] @ q) * scale.double()
+        ab += (Oq[:, k0:k0 + br].abs() @ q.abs()) * scale.double()
+    return ref.numpy() / math.sqrt(s), ab.numpy() / math.sqrt(s)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32", "bf16", "fp16", "fp8"])
+def test_sketch_entries_match_explicit_product(orc, prec):
+    """The entry-by-entry sketch (used at full size, where the whole product is
+    too slow on the CPU) against the explicit product with library-rounded
+    operands: 300 rows (two full 128-row blocks and a ragged one), columns of
+    very different scales and an all-zero block."""
+    rng = np.random.default_rng(55)
+    m, n, s, br = 300, 5, 9, 128
+    A = rng.standard_normal((m, n)) * np.array([1.0, 1e-6, 1e3, 2.0 ** -20, 7.0])
+    A[130:256, 3] = 0.0
+    A[256:, 1] = 0.0                  # the ragged block of column 1 is zero too
+    A = np.asfortranarray(A)
+    ref, ab = _explicit_sketch(orc, A, s, 17, prec, br)
+    rows, cols = np.meshgrid(np.arange(s), np.arange(n), indexing="ij")
+    got, got_abs = orc.sketch_entries(A, s, 17, rows.ravel(), cols.ravel(), prec=prec, block_rows=br)
+    np.testing.assert_allclose(got, ref.ravel(), rtol=0, atol=1e-12 * ab.ravel().max())
+    assert np.all(np.abs(got - ref.ravel()) <= 1e-11 * np.abs(ref.ravel()) + 1e-13 * ab.ravel())
+    np.testing.assert_allclose(got_abs, ab.ravel(), rtol=1e-12, atol=0)
+
+
 def test_sketch_subspace_embedding(orc):
     # For orthonormal U the sketch Omega U / sqrt(s) has singular values in
     # [1 - sqrt(n/s), 1 + sqrt(n/s)] up to fluctuations (Marchenko-Pastur).
@@ -291,7 +355,7 @@ def test_upper_solve(orc):
 # ---------------------------------------------------------------- Algorithm 1 end to end
 
 def test_pne_hpne_agree_with_qr_solver(orc):
-    # Section 6.2: in double precision PNE/HPNE are as accurate as the QR
+    # Section 7.2: in double precision PNE/HPNE are as accurate as the QR
     # solver once the relative residual exceeds 1e-4 (m = 6000, n = 100,
     # kappa = 1e4).
     for rho in [1e-3, 1e-1]:
@@ -305,7 +369,7 @@ def test_pne_hpne_agree_with_qr_solver(orc):
 
 
 def test_mixed_fp32_preconditioner_accuracy(orc):
-    # Section 6.3: with a single precision preconditioner at kappa = 1e8 the
+    # Section 7.3: with a single precision preconditioner at kappa = 1e8 the
     # error is within about a factor 100 of the QR solver for small residuals
     # and as accurate for large ones.
     for rho, factor in [(1e-8, 300.0), (1e-2, 5.0)]:
@@ -352,6 +416,94 @@ def test_refinement_restores_accuracy(orc):
     r2 = orc.solve(A, b, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
     assert relerr(r0["x"], xs) > 10 * eq       # the BF16 preconditioner alone is not enough
     assert relerr(r2["x"], xs) <= 10 * eq      # two FP64 corrections are
+
+
+def test_hpne_refinement_restores_accuracy(orc):
+    """HPNE branch of the refinement: the correction solves the HPNE system
+    with right-hand side A_p^T r (LU factors reused)."""
+    p = make_problem(3000, 50, 1e6, 1e-4, seed=24)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    eq = relerr(orc.qr_ls(A, b), xs)
+    r0 = orc.solve(A, b, hpne=True, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=0)
+    r2 = orc.solve(A, b, hpne=True, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
+    assert r0["info"] == 0 and r2["info"] == 0
+    assert relerr(r0["x"], xs) > 10 * eq
+    assert relerr(r2["x"], xs) <= 10 * eq
+    # one refinement step is one step of the stationary iteration x += M^{-1} A_p^T (b - A x)
+    # with M = A_p^T A: check the first step against that definition done with LAPACK
+    Ap, _ = orc.precondition(A, r0["R"])
+    M = Ap.T @ A
+    x1 = orc.solve(A, b, hpne=True, s=150, seed=1, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)["x"]
+    x1_ref = r0["x"] + np.linalg.solve(M, Ap.T @ (b - A @ r0["x"]))
+    assert relerr(x1, x1_ref) <= 1e-3 * relerr(r0["x"], xs)
+
+
+def _r_up_to_signs(R, Rref, ulp):
+    sg = np.sign(np.diag(R)) * np.sign(np.diag(Rref))
+    d = np.abs(R - sg[:, None] * Rref)
+    # equal except where the two factorizations' rounding straddles a tie of the narrow format
+    assert np.mean(d == 0) > 0.95
+    assert np.all(d <= ulp * np.abs(Rref) + 1e-300)
+
+
+@pytest.mark.parametrize("prec,ulp", [("bf16", 2.0 ** -7), ("fp16", 2.0 ** -10)])
+def test_low_precision_qr_path(orc, prec, ulp):
+    """qr_prec = BF16/FP16: A_s is rounded to the format (FP16 after an exact
+    power-of-two scaling), factorized, R_s rounded to the format and the
+    scale divided out.  Reference: LAPACK's QR of the library-rounded
+    sketch."""
+    p = make_problem(600, 20, 1e2, 1e-6, seed=25)
+    A, b = p.numpy_A(), p.numpy_b()
+    s = 60
+    As = orc.sketch(A, s, seed=3, prec=prec)
+    c = orc.fp16_qr_scale(As) if prec == "fp16" else 1.0
+    Aq = _lib_round(As * c, prec).numpy() if prec == "bf16" else \
+        torch.tensor((As.astype(np.float32).astype(np.float64) * c).astype(np.float32)).to(torch.float16).double().numpy()
+    Rl = np.linalg.qr(Aq, mode="r")
+    Rref = _lib_round(Rl, prec).numpy() / c
+    R = orc.solve(A, b, s=s, seed=3, sketch_prec=prec, qr_prec=prec)["R"]
+    _r_up_to_signs(R, Rref, ulp)
+
+
+def test_fp16_qr_scale_properties(orc):
+    """The FP16 QR scale is a power of two that brings max |A_s| into
+    [2^(k-1), 2^k) with k = 14 - ceil(log4 s), so every column norm of the
+    scaled sketch (and every entry of R_s) stays below 2^14 < 65504."""
+    rng = np.random.default_rng(26)
+    for s, n, mag in [(60, 20, 1.0), (3000, 40, 1e9), (300, 100, 1e-9), (257, 3, 3.0)]:
+        As = rng.standard_normal((s, n)) * mag
+        c = orc.fp16_qr_scale(As)
+        m, e = math.frexp(c)
+        assert m == 0.5                                  # a power of two
+        k = 14 - math.ceil(math.log(s, 4) - 1e-12)
+        amax = np.abs(As.astype(np.float32)).max() * c
+        assert 2.0 ** (k - 1) <= amax < 2.0 ** k
+        assert np.linalg.norm(As * c, axis=0).max() < 2.0 ** 14
+        assert orc.fp16_qr_scale(As * 2.0 ** 20) == c * 2.0 ** -20
+    assert orc.fp16_qr_scale(np.zeros((10, 2))) == 1.0
+
+
+def test_fp16_preconditioner_is_scale_invariant(orc):
+    """Algorithm 1 picks u_p from kappa alone: a well-conditioned problem with
+    huge or tiny entries solves with the FP16 preconditioner as accurately as
+    the unscaled one (x scales with 1/c for A -> c A)."""
+    p = make_problem(2000, 40, 1e2, 1e-6, seed=27)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    for c in (1.0, 1e6, 1e-6):
+        eq = relerr(orc.qr_ls(c * A, b), xs / c)
+        r = orc.solve(c * A, b, s=120, seed=1, sketch_prec="fp16", qr_prec="fp16", refine_steps=2)
+        assert r["info"] == 0
+        assert np.all(np.isfinite(r["R"]))
+        assert relerr(r["x"], xs / c) <= 10 * eq
+
+
+def test_lu_nan_pivot_reports_breakdown(orc):
+    C = np.array([[2.0, 1.0, 0.0], [1.0, np.nan, 1.0], [0.0, 1.0, 3.0]])
+    _, piv, info = orc.lu(C)
+    assert info == 3002
+    assert np.all((piv >= 0) & (piv < 3))
+    C2 = np.array([[np.nan, 1.0], [5.0, 2.0]])
+    assert orc.lu(C2)[2] == 3001
 
 
 # ---------------------------------------------------------------- condition estimate
