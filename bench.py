@@ -45,6 +45,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--quick", action="store_true", help="mixed path only (profiling runs)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 512-problem batched measurement")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the m = 1e6 (AUTO) and m = 4e6 (FP8 HPNE) single-problem measurements")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 512-problem batched measurement (profiling runs); prints its JSON object")
     ap.add_argument("--copy-probe", action="store_true",
@@ -172,6 +174,39 @@ def time_batched(pne, steps, warmup):
     return out
 
 
+def host_cpu():
+    """Core count and CPU model of the host the oracle runs on."""
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model}
+
+
+def oracle_config1():
+    """The oracle's whole solve of the m = 1000, n = 100 problem (kappa 1e8,
+    rho 1e-6, s = 300, FP32 preconditioner, one refinement step), and its QR
+    solver on the same problem: wall seconds and errors."""
+    import numpy as np
+
+    import oracle
+    from workloads import make_problem
+    p = make_problem(1000, 100, 1e8, 1e-6, seed=1001)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    t0 = time.perf_counter()
+    r = oracle.solve(A, b, s=300, seed=1, sketch_prec="fp32", qr_prec="fp32", refine_steps=1)
+    t1 = time.perf_counter()
+    xq = oracle.qr_ls(A, b)
+    t2 = time.perf_counter()
+    rel = lambda x: float(np.linalg.norm(x - xs) / np.linalg.norm(xs))
+    return {"pne_s": round(t1 - t0, 4), "pne_rel_err": rel(r["x"]), "qr_ls_s": round(t2 - t1, 4),
+            "qr_ls_rel_err": rel(xq)}
+
+
 def cpu_baseline(prob, ms_rows=5000):
     """Oracle (plain single-threaded C, FP64 with BF16 operand emulation) timed
     per step on the first `ms_rows` rows of the same A; the row-proportional
@@ -207,12 +242,62 @@ def cpu_baseline(prob, ms_rows=5000):
     # the sketch and are not timed
     per_solve = scale * (t["sketch"] + t["trsm"] + t["gram"]) + t["qr"] + 2 * t["factor_solve"]
     sample_s = sum(t.values())
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle",
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle", "host": host_cpu(),
+            "config1_whole_solve": oracle_config1(),
             "sample": (f"oracle steps on the first {ms_rows} of {M} rows (n={N}, s={S}, BF16 operand "
                        f"emulation, single thread, {sample_s:.1f} s of CPU work); row-proportional steps "
                        f"(sketch, A R^-1, Gram) scaled by {scale:.0f}x, QR/Cholesky/"
                        f"solves as measured"),
             "phase_seconds": {k: round(v, 3) for k, v in t.items()}}
+
+
+def time_large(pne, steps, warmup):
+    """The two largest single-problem workloads (generated on the device):
+    m = 1e6, n = 2000, kappa = 1e10 (half the singular values 1), rho = 1e-8,
+    s = 6000: AUTO precision with one refinement step, and the forced FP32
+    preconditioner with one step; m = 4e6, n = 1000, kappa = 1e8, rho = 1e-6,
+    s = 4000: HPNE with an FP8 e4m3 sketch (per-128-row-block scales), FP32
+    QR and two refinement steps, against the all-FP64 HPNE."""
+    import gc
+
+    import torch
+
+    from workloads import make_problem
+    out = {}
+    p3 = make_problem(1_000_000, 2000, 1e10, 1e-8, seed=1003, sigma="half_ones", device="cuda")
+    torch.cuda.synchronize()
+    b3 = 1e10 * U64 * (1 + 1e10 * 1e-8)
+    rows = {}
+    for name, o, hp in [("auto_pne_refine1", pne.make_opts(s=6000, seed=3, sketch_prec="auto", qr_prec="auto",
+                                                            refine_steps=1), False),
+                        ("fp32_pne_refine1", pne.make_opts(s=6000, seed=3, sketch_prec="fp32", qr_prec="fp32",
+                                                           refine_steps=1), False)]:
+        print(f"[bench] timing m=1e6 n=2000 {name}", file=sys.stderr, flush=True)
+        t, e, _ = time_solver(pne, p3, o, steps, warmup, hpne=hp)
+        _, _, meta = pne.pne_solve(p3.A, p3.b, opts=o)
+        rows[name] = {"solves_per_s": 1.0 / t, "ms": t * 1e3, "rel_err": e, "precision": meta["qr_prec"]}
+    out["ls_1000000x2000_k1e10"] = dict(rows, lemma_bound=b3)
+    p3.At = p3.b = p3.x_star = None
+    del p3
+    gc.collect()
+    torch.cuda.empty_cache()
+    p5 = make_problem(4_000_000, 1000, 1e8, 1e-6, seed=1005, device="cuda")
+    torch.cuda.synchronize()
+    b5 = 1e8 * U64 * (1 + 1e8 * 1e-6)
+    rows = {}
+    for name, o in [("fp8_hpne_refine2", pne.make_opts(s=4000, seed=5, sketch_prec="fp8", qr_prec="fp32",
+                                                       refine_steps=2)),
+                    ("fp64_hpne", pne.make_opts(s=4000, seed=5, sketch_prec="fp64", qr_prec="fp64",
+                                                refine_steps=0))]:
+        print(f"[bench] timing m=4e6 n=1000 {name}", file=sys.stderr, flush=True)
+        t, e, _ = time_solver(pne, p5, o, steps, warmup, hpne=True)
+        rows[name] = {"solves_per_s": 1.0 / t, "ms": t * 1e3, "rel_err": e}
+    out["ls_4000000x1000_k1e8"] = dict(rows, lemma_bound=b5)
+    p5.At = p5.b = p5.x_star = None
+    del p5
+    gc.collect()
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -255,13 +340,19 @@ def main():
         print("[bench] timing FP32-preconditioner PNE", file=sys.stderr, flush=True)
         t32, e32, _ = time_solver(pne, prob, fp32, args.steps, args.warmup)
         print("[bench] timing mixed HPNE", file=sys.stderr, flush=True)
-        th, eh, _ = time_solver(pne, prob, mixed, args.steps, args.warmup, hpne=True)
+        th, eh, phh = time_solver(pne, prob, mixed, args.steps, args.warmup, hpne=True, profile=True)
+        print("[bench] timing FP64 HPNE", file=sys.stderr, flush=True)
+        th64, eh64, phh64 = time_solver(pne, prob, fp64, args.steps, args.warmup, hpne=True, profile=True)
         out_extra = {
             "fp64_pne": {"solves_per_s": 1.0 / t64, "ms": t64 * 1e3, "rel_err": e64,
                          "phases_ms": {k: round(v, 4) for k, v in mean_phases(ph64).items()}},
             "fp32_precond_pne": {"solves_per_s": 1.0 / t32, "ms": t32 * 1e3, "rel_err": e32},
-            "mixed_hpne": {"solves_per_s": 1.0 / th, "ms": th * 1e3, "rel_err": eh},
+            "mixed_hpne": {"solves_per_s": 1.0 / th, "ms": th * 1e3, "rel_err": eh,
+                           "phases_ms": {k: round(v, 4) for k, v in mean_phases(phh).items()}},
+            "fp64_hpne": {"solves_per_s": 1.0 / th64, "ms": th64 * 1e3, "rel_err": eh64,
+                          "phases_ms": {k: round(v, 4) for k, v in mean_phases(phh64).items()}},
             "speedup_vs_fp64": t64 / t_mix,
+            "hpne_speedup_vs_fp64": th64 / th,
             "equal_error": bool(e_mix <= 10 * max(e64, bound * 1e-3) and e_mix <= 10 * bound),
         }
     line = {
@@ -286,6 +377,8 @@ def main():
         del prob
         torch.cuda.empty_cache()
         line["batch512"] = time_batched(pne, max(2, args.steps // 2), 1)
+    if not args.quick and not args.no_large:
+        line["large"] = time_large(pne, 2, 1)
     print(json.dumps(line))
 
 

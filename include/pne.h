@@ -8,7 +8,7 @@
  *   PNE  (Section 1, eq. e_pne):  A_p^T A_p y = A_p^T b,  R_s x = y
  *   HPNE (Section 1, eq. e_hpne): A_p^T A x = A_p^T b
  *   with A_p = A R_s^{-1} and R_s the triangular factor of a sketch
- *   Omega A (Algorithm 1; Section 5.2), computed in a lower precision.
+ *   Omega A (Algorithm 1; Section 6.2), computed in a lower precision.
  *
  * Common conventions for every entry point.
  *   - All matrices are column-major with a leading dimension (LAPACK); A has
@@ -28,9 +28,12 @@
  *     device work and returned as a negative pne_status; nothing is enqueued.
  *   - Numerical failures are reported asynchronously in the device word
  *     *dinfo (LAPACK style): 0 success; 1000+k: R_s(k,k) == 0; 2000+k:
- *     Cholesky of the PNE matrix broke down at column k; 3000+k: zero pivot
- *     in the LU of the HPNE matrix at column k (k 1-based).  On failure x is
- *     filled with NaN; no silent fallback to another precision is taken.
+ *     Cholesky of the PNE matrix broke down at column k; 3000+k: zero or
+ *     non-finite pivot in the LU of the HPNE matrix at column k (k 1-based);
+ *     4000+k: a block of the parallel triangular solves gave up waiting for
+ *     block k (a scheduling failure; the result is invalid).  R_s(k,k) counts
+ *     as zero when it is not finite.  On failure x is filled with NaN; no
+ *     silent fallback to another precision is taken.
  *   - Same inputs and options give bitwise identical results (every
  *     reduction has a fixed order; no floating-point atomics).
  */
@@ -57,7 +60,7 @@ typedef enum {
 
 /* Arithmetic of the preconditioner (Algorithm 1, "precision u_p"). */
 typedef enum {
-    PNE_PREC_AUTO = 0,     /* pick by the FP32 condition estimate (Section 5.1)  */
+    PNE_PREC_AUTO = 0,     /* pick by the FP32 condition estimate (Section 6.1)  */
     PNE_PREC_FP64 = 1,
     PNE_PREC_FP32 = 2,
     PNE_PREC_FP16 = 3,     /* FP16 operands, per-block power-of-two scales of A   */
@@ -66,7 +69,7 @@ typedef enum {
 } pne_prec;
 
 typedef struct {
-    int64_t s;              /* sketch rows; 0 selects 3n (Section 5.2 uses d = 3n)       */
+    int64_t s;              /* sketch rows; 0 selects 3n (Section 6.2 uses d = 3n)       */
     uint64_t seed;          /* key of the counter-based Gaussian sketch                  */
     uint32_t problem_id;    /* third counter word of the sketch (batch member index)     */
     int32_t sketch_prec;    /* pne_prec of the sketch Omega A                            */
@@ -119,7 +122,7 @@ pne_status hpne_solve(int64_t m, int64_t n, const double* dA, int64_t lda, const
                       int32_t* dinfo, pne_info* hinfo, pne_stream_t stream);
 
 /* sketch_precond: the preconditioner alone (Algorithm 1 steps "Sketch",
- * "Thin QR", "Promote R_s"; Section 5.2).  Writes the upper triangle of the
+ * "Thin QR", "Promote R_s"; Section 6.2).  Writes the upper triangle of the
  * n x n FP64 matrix R_s into dR (ldr >= n); the strict lower triangle is set
  * to zero.  Workspace: sketch_precond_workspace_size. */
 size_t sketch_precond_workspace_size(int64_t m, int64_t n, const pne_opts* opts);
@@ -127,7 +130,7 @@ pne_status sketch_precond(int64_t m, int64_t n, const double* dA, int64_t lda, c
                           double* dR, int64_t ldr, void* dwork, size_t work_bytes, int32_t* dinfo,
                           pne_info* hinfo, pne_stream_t stream);
 
-/* cond_est: the single-precision condition estimate of Section 5.1 and the
+/* cond_est: the single-precision condition estimate of Section 6.1 and the
  * precision pick of Algorithm 1.  G = fl32(A)^T fl32(A) (FP32), FP32
  * Cholesky, Hager's 1-norm estimate of ||G^{-1}||_1 (at most five
  * iterations), kappa0 = (1/2) log10(||G||_1 est) written to *dkappa0 (device
@@ -150,11 +153,13 @@ pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64
 /* Batched PNE/HPNE (many independent problems in one call).
  * Problem i is A_i (m_i x n_i, lda_i) at dA_base + a_offset_i doubles, b_i at
  * db_base + b_offset_i, x_i written at dx_base + x_offset_i.  All problems
- * share the options; problem_id = i for the sketch of member i.  dinfo has
+ * share the options except the sketch counter word: member i draws its
+ * sketch with problem_id_i (opts->problem_id is ignored).  dinfo has
  * `batch` device int32 words.  hdesc is a host array. */
 typedef struct {
     int64_t m, n, lda;
     int64_t a_offset, b_offset, x_offset;
+    int64_t problem_id;   /* third counter word of member i's sketch (0 .. 2^32 - 1) */
 } pne_problem_desc;
 
 size_t pne_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc,
@@ -163,6 +168,22 @@ pne_status pne_solve_batched(int64_t batch, const pne_problem_desc* hdesc, const
                              const double* db_base, double* dx_base, const pne_opts* opts,
                              int hpne, void* dwork, size_t work_bytes, int32_t* dinfo,
                              pne_stream_t stream);
+
+/* pne_gram: the normal-equation matrices of the solvers for a given
+ * preconditioner (diagnostics and kernel-level checks).  With R (n x n,
+ * upper triangle read, ldr >= n, FP64): A_p = A R^{-1} (Algorithm 1, "Solve
+ * A_p"); C = A_p^T A_p (hpne = 0, eq. e_pne; only the lower triangle of C is
+ * defined) or C = A_p^T A (hpne = 1, eq. e_hpne); c = A_p^T b.  With
+ * factor != 0, C is then factored in place as the solvers do: the Cholesky
+ * factor L in the lower triangle (PNE), or P C = L U with unit lower L below
+ * the diagonal, U on and above it and the 0-based pivot rows in dpiv[n]
+ * (HPNE; LAPACK ordering).  dC: n x n (ldc >= n); dc: n; dinfo: one device
+ * int32 (2000+k / 3000+k on a breakdown, as the solvers).  Workspace:
+ * pne_gram_workspace_size. */
+size_t pne_gram_workspace_size(int64_t m, int64_t n, int hpne);
+pne_status pne_gram(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db, const double* dR,
+                    int64_t ldr, int hpne, int factor, double* dC, int64_t ldc, double* dc, int32_t* dpiv,
+                    void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream);
 
 /* Phase timing (diagnostics).  pne_profile_enable(1) makes every following
  * solve record a HIP event on its stream after each phase of the pipeline

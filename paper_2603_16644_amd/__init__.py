@@ -4,8 +4,8 @@ least-squares problems (Garrison & Ipsen, arXiv 2603.16644).
 The solver lives in the HIP library libpne.so behind the C ABI of
 include/pne.h; this package is its Python binding.
 """
-from ._lib import (PREC, Opts, PneError, cond_est, hpne_solve, lib, make_opts, pne_sketch,
+from ._lib import (PREC, Opts, PneError, cond_est, hpne_solve, lib, make_opts, pne_gram, pne_sketch,
                    pne_solve, pne_solve_batched, sketch_precond)
 
-__all__ = ["PREC", "Opts", "PneError", "cond_est", "hpne_solve", "lib", "make_opts", "pne_sketch",
+__all__ = ["PREC", "Opts", "PneError", "cond_est", "hpne_solve", "lib", "make_opts", "pne_gram", "pne_sketch",
            "pne_solve", "pne_solve_batched", "sketch_precond"]

@@ -26,8 +26,8 @@ STATUS = {0: "ok", -1: "invalid argument", -2: "out of host memory", -3: "HIP ru
 EXPORTS = ["pne_default_opts", "pne_workspace_size", "pne_solve", "hpne_solve",
            "sketch_precond_workspace_size", "sketch_precond", "cond_est_workspace_size", "cond_est",
            "pne_sketch_workspace_size", "pne_sketch", "pne_batched_workspace_size",
-           "pne_solve_batched", "pne_status_string", "pne_profile_enable", "pne_profile_read",
-           "pne_profile_phase_name"]
+           "pne_solve_batched", "pne_gram_workspace_size", "pne_gram", "pne_status_string",
+           "pne_profile_enable", "pne_profile_read", "pne_profile_phase_name"]
 
 
 class PneError(RuntimeError):
@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
 class ProblemDesc(ctypes.Structure):
     _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("lda", ctypes.c_int64),
                 ("a_offset", ctypes.c_int64), ("b_offset", ctypes.c_int64),
-                ("x_offset", ctypes.c_int64)]
+                ("x_offset", ctypes.c_int64), ("problem_id", ctypes.c_int64)]
 
 
 _lib = None
@@ -80,6 +80,9 @@ def lib():
                                           ctypes.c_int32, ctypes.c_int32, P, i64, P, sz, P]),
             "pne_batched_workspace_size": (sz, [i64, P, OP, ctypes.c_int]),
             "pne_solve_batched": (ctypes.c_int, [i64, P, P, P, P, OP, ctypes.c_int, P, sz, P, P]),
+            "pne_gram_workspace_size": (sz, [i64, i64, ctypes.c_int]),
+            "pne_gram": (ctypes.c_int, [i64, i64, P, i64, P, P, i64, ctypes.c_int, ctypes.c_int, P, i64, P, P,
+                                        P, sz, P, P]),
             "pne_status_string": (ctypes.c_char_p, [ctypes.c_int]),
             "pne_profile_enable": (ctypes.c_int, [ctypes.c_int]),
             "pne_profile_read": (ctypes.c_int, [P, ctypes.c_int]),
@@ -227,12 +230,15 @@ def pne_sketch(A, s: int, seed: int = 0, problem_id: int = 0, prec="fp64", block
 def pne_solve_batched(A_base, b_base, x_base, descs, opts: Opts | None = None, hpne: bool = False,
                       stream=None, workspace=None):
     """Batched solve over problems described by `descs` (list of dicts with m, n,
-    lda, a_offset, b_offset, x_offset in float64 elements).  Returns info (batch,)."""
+    lda, a_offset, b_offset, x_offset in float64 elements and an optional
+    problem_id, the sketch counter word, default the list index).  Returns
+    info (batch,)."""
     opts = opts or make_opts()
     batch = len(descs)
     arr = (ProblemDesc * batch)()
     for i, d in enumerate(descs):
-        arr[i] = ProblemDesc(d["m"], d["n"], d["lda"], d["a_offset"], d["b_offset"], d["x_offset"])
+        arr[i] = ProblemDesc(d["m"], d["n"], d["lda"], d["a_offset"], d["b_offset"], d["x_offset"],
+                             d.get("problem_id", i))
     info = torch.zeros(batch, dtype=torch.int32, device=A_base.device)
     need = lib().pne_batched_workspace_size(batch, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
                                             int(hpne))
@@ -244,3 +250,24 @@ def pne_solve_batched(A_base, b_base, x_base, descs, opts: Opts | None = None, h
                                  info.data_ptr(), _stream_ptr(stream))
     _check("pne_solve_batched", rc)
     return info
+
+
+def pne_gram(A, b, R, hpne: bool = False, factor: bool = False, stream=None, workspace=None):
+    """Normal-equation matrix for a given preconditioner R (include/pne.h
+    pne_gram).  Returns (C (n x n column-major view), c, piv or None, info)."""
+    m, n, lda = _colmajor(A)
+    if R.shape != (n, n) or R.dtype != torch.float64 or R.stride(0) != 1:
+        raise ValueError("R must be an n x n column-major float64 CUDA tensor")
+    Ct = torch.empty(n, n, dtype=torch.float64, device=A.device)
+    c = torch.empty(n, dtype=torch.float64, device=A.device)
+    piv = torch.empty(n, dtype=torch.int32, device=A.device) if (hpne and factor) else None
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    need = lib().pne_gram_workspace_size(m, n, int(hpne))
+    if need == 0:
+        raise PneError("pne_gram_workspace_size", -1)
+    ws = (workspace or _ws).get(need, A.device)
+    rc = lib().pne_gram(m, n, A.data_ptr(), lda, b.data_ptr(), R.data_ptr(), R.stride(1), int(hpne), int(factor),
+                        Ct.data_ptr(), n, c.data_ptr(), piv.data_ptr() if piv is not None else None,
+                        ws.data_ptr(), ws.numel(), info.data_ptr(), _stream_ptr(stream))
+    _check("pne_gram", rc)
+    return Ct.t(), c, piv, info

@@ -201,18 +201,15 @@ pne_status run_precond(Exec& ex, const Problem& p, const double* dA, uint64_t se
     return (pne_status)rc;
 }
 
-// A_p, Gram, factorization, solves and refinement (Algorithm 1 after the
-// preconditioner) for one problem.
-pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double* db, double* dx,
-                     const Buffers& b, int32_t* dinfo)
+// A_p = A R_s^{-1}, C = A_p^T A_p (PNE, lower tiles) or A_p^T A (HPNE) and
+// c = A_p^T b (Algorithm 1 "Solve A_p" and the normal-equation matrices).
+void run_gram(Exec& ex, const Problem& p, const double* dA, const double* db, const Buffers& b)
 {
     const int64_t m = p.m, n = p.n, lda = p.lda;
     const int hpne = p.hpne;
-    // A_p = A R_s^{-1}
     ex.stage(ST_TRSM);
     trsm_right_upper(ex, m, n, dA, lda, b.R, n, b.Ap, m);
     mark(ex, PH_TRSM);
-    // C = A_p^T A_p (PNE, lower tiles) or A_p^T A (HPNE); c = A_p^T b
     ex.stage(ST_GRAM);
     int64_t splits, kc;
     const int64_t gtiles = gemm_tiles(n, n, m, !hpne);
@@ -233,6 +230,14 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     ex.stage(ST_GRAM_REDUCE);
     gemm_f64_reduce(ex, g);
     mark(ex, PH_GRAM_REDUCE);
+}
+
+// Cholesky (PNE) or LU with partial pivoting (HPNE) of C in place, then the
+// inverses of the 64 x 64 diagonal blocks the triangular solves use.
+void run_factor(Exec& ex, const Problem& p, const Buffers& b, int32_t* dinfo)
+{
+    const int64_t n = p.n;
+    const int hpne = p.hpne;
     ex.stage(ST_FACTOR);
     if (hpne) lu_factor(ex, n, b.C, n, b.piv, dinfo);
     else cholesky<double>(ex, n, b.C, n, dinfo, b.dinv1);
@@ -246,17 +251,28 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
         transpose_dinv(ex, n, b.dinv1, b.dinv1t);
     }
     mark(ex, PH_FACTOR);
+}
+
+// A_p, Gram, factorization, solves and refinement (Algorithm 1 after the
+// preconditioner) for one problem.
+pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double* db, double* dx,
+                     const Buffers& b, int32_t* dinfo)
+{
+    const int64_t m = p.m, n = p.n, lda = p.lda;
+    const int hpne = p.hpne;
+    run_gram(ex, p, dA, db, b);
+    run_factor(ex, p, b, dinfo);
     ex.stage(ST_SOLVE);
-    if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, b.flags);
-    else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx, b.t, b.flags);
+    if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.c, dx, b.flags, dinfo);
+    else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.c, dx, b.t, b.flags, dinfo);
     mark(ex, PH_SOLVE);
     ex.stage(ST_REFINE);
     for (int k = 0; k < p.refine; ++k) {
         ex.iter((uint32_t)k);
         residual(ex, m, n, dA, lda, db, dx, b.r);
         gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
-        if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, b.flags);
-        else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.t, b.flags);
+        if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, b.flags, dinfo);
+        else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.t, b.flags, dinfo);
         axpy_update(ex, n, dx, b.d);
     }
     ex.stage(ST_FINISH);
@@ -367,7 +383,8 @@ pne_status record_batch(Recorder& rec, int64_t batch, const pne_problem_desc* hd
         const double* A = dA_base ? dA_base + hd[i].a_offset : nullptr;
         const double* b = db_base ? db_base + hd[i].b_offset : nullptr;
         double* x = dx_base ? dx_base + hd[i].x_offset : nullptr;
-        pne_status rc = run_precond(ex, p, A, o->seed, (uint32_t)i, sk[i], qr[i], L.buf[i], dinfo ? dinfo + i : nullptr);
+        pne_status rc = run_precond(ex, p, A, o->seed, (uint32_t)hd[i].problem_id, sk[i], qr[i], L.buf[i],
+                                     dinfo ? dinfo + i : nullptr);
         if (rc) return rc;
         rc = run_solve(ex, p, A, b, x, L.buf[i], dinfo ? dinfo + i : nullptr);
         if (rc) return rc;
@@ -400,6 +417,7 @@ pne_status check_batch(int64_t batch, const pne_problem_desc* hd, const pne_opts
         pne_status chk = check_common(d.m, d.n, (const void*)1, d.lda, o);
         if (chk) return chk;
         if (d.a_offset < 0 || d.b_offset < 0 || d.x_offset < 0) return PNE_EINVAL;
+        if (d.problem_id < 0 || d.problem_id > (int64_t)UINT32_MAX) return PNE_EINVAL;
         if (hpne && !lu_supported(d.n)) return PNE_ENOTSUP;
     }
     return PNE_OK;
@@ -604,6 +622,46 @@ pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64
     ex.st = (hipStream_t)stream;
     return (pne_status)sketch_run(ex, m, n, dA, lda, s, seed, problem_id, prec, br, nullptr, 0, dAs, ldas,
                                   dwork, work_bytes);
+}
+
+static Problem gram_problem(int64_t m, int64_t n, int64_t lda, int hpne)
+{
+    pne_opts o;
+    pne_default_opts(&o);
+    o.s = n;
+    o.sketch_prec = PNE_PREC_FP64;
+    o.qr_prec = PNE_PREC_FP64;
+    o.refine_steps = 0;
+    return make_problem(m, n, lda, &o, hpne);
+}
+
+size_t pne_gram_workspace_size(int64_t m, int64_t n, int hpne)
+{
+    if (n < 1 || m < n || n > 4096) return 0;
+    return layout(gram_problem(m, n, m, hpne), nullptr, 0, nullptr, false);
+}
+
+pne_status pne_gram(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db, const double* dR,
+                    int64_t ldr, int hpne, int factor, double* dC, int64_t ldc, double* dc, int32_t* dpiv,
+                    void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream)
+{
+    if (!dA || !db || !dR || !dC || !dc || !dinfo || !dwork) return PNE_EINVAL;
+    if (n < 1 || m < n || lda < m || ldr < n || ldc < n) return PNE_EINVAL;
+    if (n > 4096) return PNE_ENOTSUP;
+    if (hpne && factor && !dpiv) return PNE_EINVAL;
+    Problem p = gram_problem(m, n, lda, hpne ? 1 : 0);
+    Buffers b;
+    if (work_bytes < layout(p, dwork, work_bytes, &b, false)) return PNE_EWORKSPACE;
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    zero_i32(ex, 1, dinfo);
+    copy_f64(ex, n, n, dR, ldr, b.R, n);
+    run_gram(ex, p, dA, db, b);
+    if (factor) run_factor(ex, p, b, dinfo);
+    copy_f64(ex, n, n, b.C, n, dC, ldc);
+    copy_f64(ex, n, 1, b.c, n, dc, n);
+    if (factor && hpne) copy_i32(ex, n, b.piv, dpiv);
+    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
 }
 
 size_t pne_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* o, int hpne)

@@ -1,4 +1,4 @@
-// Single-precision condition estimate and precision pick (Section 5.1,
+// Single-precision condition estimate and precision pick (Section 6.1,
 // Algorithm 1 first step).
 //   G = fl32(A)^T fl32(A)       FP32 MFMA SYRK, split over rows of A
 //   ||G||_1                     max column sum of |G| (symmetric, lower stored)
@@ -17,7 +17,7 @@
 // The factor n of the bound kappa(A)^2 <= n ||G||_1 ||G^{-1}||_1 is left out
 // of kappa0 (with it, kappa(A) = 1e2 would select single precision for
 // 400 <= n <= 2000, contrary to the half-precision pick reported in
-// Section 6.4).
+// Section 7.4).
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"

@@ -117,13 +117,14 @@ void inv_diag_blocks(Exec& ex, int64_t n, const T* M, int64_t ld, int lower, int
 // lower L), with the inverses DL, DLt, DR, DU of the 64 x 64 diagonal blocks;
 // one work-group per 64-row block and per-block flags (flags: 3 *
 // lb_flag_words(n) int32 for the PNE solve, 2 * ... for the LU solve; any
-// contents on entry).  c and x may alias.
+// contents on entry).  c and x may alias.  A wait between blocks that gives
+// up writes 4000 + block + 1 to *info (if still zero; info may be null).
 size_t lb_flag_words(int64_t n);
 void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                   const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
-                  double* y, int32_t* flags);   // y: n-vector scratch (L^T y = z)
+                  double* y, int32_t* flags, int32_t* info);   // y: n-vector scratch (L^T y = z)
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
-                 const double* DU, const double* c, double* x, int32_t* flags);
+                 const double* DU, const double* c, double* x, int32_t* flags, int32_t* info);
 // out (c x r, ldo) = in^T (in r x c, ldi)
 void transpose_f64(Exec& ex, int64_t r, int64_t c, const double* in, int64_t ldi, double* out, int64_t ldo);
 // transposes of the 64 x 64 blocks of a block-inverse array (dinv_elems(n))
@@ -141,6 +142,7 @@ void fill_nan_on_info(Exec& ex, int64_t n, double* x, const int32_t* info);
 // dst(:, j) = src(:, j) for an r x c column-major block
 void copy_f64(Exec& ex, int64_t r, int64_t c, const double* src, int64_t lds, double* dst, int64_t ldd);
 void zero_i32(Exec& ex, int64_t n, int32_t* p);
+void copy_i32(Exec& ex, int64_t n, const int32_t* src, int32_t* dst);
 
 // ---------------------------------------------------------------- batches
 // Merge the recorded launches of a batch into grouped launches, copy their

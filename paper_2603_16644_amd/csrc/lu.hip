@@ -9,7 +9,8 @@
 //   the same row exchanges are applied to the other columns;
 //   U12 := L11^{-1} C12 (unit lower, row-parallel leaf on U12^T);
 //   C22 -= L21 U12 (MFMA GEMM).
-// A zero pivot at global column k sets *info = 3000 + k + 1 (first only).
+// A zero or non-finite pivot at global column k sets *info = 3000 + k + 1
+// (first only); that column's elimination is skipped.
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -55,7 +56,8 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
         for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
     }
     for (int k = 0; k < w; ++k) {
-        // argmax |x(r, k)| over r >= k, first index on ties
+        // argmax |x(r, k)| over r >= k, first index on ties; a NaN counts as
+        // +inf, so a column holding one selects a non-finite pivot
         double best = -1.0;
         int64_t bidx = INT64_MAX;
 #pragma unroll
@@ -65,6 +67,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
             for (int c = 0; c < PW; ++c)
                 if (c == k) v = fabs(x[q][c]);
+            if (v != v) v = INFINITY;
             if (r >= k && r < h && v > best) { best = v; bidx = r; }
         }
 #pragma unroll
@@ -80,6 +83,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             int64_t bi = wi[0];
             for (int i = 1; i < LU_WAVES; ++i)
                 if (wv[i] > b || (wv[i] == b && wi[i] < bi)) { b = wv[i]; bi = wi[i]; }
+            if (bi < k || bi >= h) bi = k;   // no candidate: keep the row in place
             pivsh = bi;
             piv[c0 + k] = (int32_t)(c0 + bi);
         }
@@ -111,7 +115,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
         for (int c = 0; c < PW; ++c)
             if (c == k) pv = rowP[c];
-        if (pv == 0.0) {
+        if (pv == 0.0 || !isfinite(pv)) {
             if (tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
         } else {
 #pragma unroll

@@ -4,26 +4,33 @@
 // never synchronises the stream.
 #include <string.h>
 
+#include <vector>
+
 #include "common.h"
 #include "profile.h"
 
 namespace pne {
 
+// Every mark records one event of a pool in order; the time between a mark
+// and the previous one is charged to the later mark's phase, so a phase that
+// recurs (the chunks of a long sketch) accumulates its pieces.
 static bool g_prof_on = false;
-static bool g_prof_ready = false;
-static hipEvent_t g_ev[PH_COUNT];
-static bool g_marked[PH_COUNT];
+static std::vector<hipEvent_t> g_pool;
+static std::vector<int> g_phase;   // phase of each recorded event, in order
 
 void prof_mark(int phase, hipStream_t st)
 {
     if (!g_prof_on || phase < 0 || phase >= PH_COUNT) return;
-    if (hipEventRecord(g_ev[phase], st) == hipSuccess) g_marked[phase] = true;
+    const size_t k = g_phase.size();
+    if (k == g_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        g_pool.push_back(e);
+    }
+    if (hipEventRecord(g_pool[k], st) == hipSuccess) g_phase.push_back(phase);
 }
 
-void prof_reset()
-{
-    for (int i = 0; i < PH_COUNT; ++i) g_marked[i] = false;
-}
+void prof_reset() { g_phase.clear(); }
 
 }  // namespace pne
 
@@ -37,12 +44,7 @@ static const char* k_phase_names[PH_COUNT] = {
 
 int pne_profile_enable(int enable)
 {
-    if (enable && !g_prof_ready) {
-        for (int i = 0; i < PH_COUNT; ++i)
-            if (hipEventCreate(&g_ev[i]) != hipSuccess) return PNE_EHIP;
-        g_prof_ready = true;
-    }
-    g_prof_on = enable != 0 && g_prof_ready;
+    g_prof_on = enable != 0;
     prof_reset();
     return PNE_OK;
 }
@@ -51,18 +53,16 @@ const char* pne_profile_phase_name(int i) { return (i >= 0 && i < PH_COUNT) ? k_
 
 int pne_profile_read(double* ms, int max_phases)
 {
-    if (!g_prof_ready) return 0;
-    int count = max_phases < PH_COUNT ? max_phases : PH_COUNT;
+    const int count = max_phases < PH_COUNT ? max_phases : PH_COUNT;
     for (int i = 0; i < count; ++i) ms[i] = -1.0;
-    int prev = -1;
-    for (int i = 0; i < PH_COUNT; ++i) {
-        if (!g_marked[i]) continue;
-        if (hipEventSynchronize(g_ev[i]) != hipSuccess) return PNE_EHIP;
-        if (prev >= 0 && i < count) {
-            float t = 0.0f;
-            if (hipEventElapsedTime(&t, g_ev[prev], g_ev[i]) == hipSuccess) ms[i] = t;
-        }
-        prev = i;
+    if (g_phase.empty()) return g_prof_on ? count : 0;
+    if (hipEventSynchronize(g_pool[g_phase.size() - 1]) != hipSuccess) return PNE_EHIP;
+    for (size_t k = 1; k < g_phase.size(); ++k) {
+        const int ph = g_phase[k];
+        if (ph >= count) continue;
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, g_pool[k - 1], g_pool[k]) != hipSuccess) return PNE_EHIP;
+        ms[ph] = (ms[ph] < 0.0 ? 0.0 : ms[ph]) + t;
     }
     return count;
 }

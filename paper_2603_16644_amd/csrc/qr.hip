@@ -1,5 +1,5 @@
 // Householder QR of the s x n sketch A_s keeping only R_s (Algorithm 1,
-// "Thin QR factorization A_s = Q_s R_s"; Section 5.2), then the promotion of
+// "Thin QR factorization A_s = Q_s R_s"; Section 6.2), then the promotion of
 // R_s to FP64 (Algorithm 1, "Promote R_s").
 //
 // Blocked compact-WY form (Golub & Van Loan, Section 5.2.3):
@@ -13,7 +13,8 @@
 //           wavefront per trailing column).
 // Working precision: FP64 for qr_prec = FP64, FP32 otherwise.  For BF16 and
 // FP16 the input is rounded to the format before the factorization and R_s
-// after it (FP32 arithmetic in between).
+// after it (FP32 arithmetic in between); FP16 input is first scaled by a
+// power of two that keeps R_s inside the FP16 range (QrScale).
 #include "common.h"
 #include "convert.h"
 #include "kernels.h"
@@ -599,11 +600,59 @@ struct QrApply {
     }
 };
 
+// FP16 QR input scale (single work-group): c = 2^(k - E) with amax =
+// max |W| = f 2^E (f in [1/2, 1)) and k = 14 - t, 4^t the smallest power of
+// four >= s.  Then |c W| < 2^k <= 2^14 / sqrt(s), every column of c W has
+// 2-norm below 2^14, and so has every entry of its triangular factor: the
+// FP16 range (largest finite 65504) holds R_s whatever the scale of A.  The
+// factor is exact (a power of two) and is divided out of R_s again in FP64.
+// amax = 0 or non-finite gives c = 1.
+struct QrScaleArgs {
+    int64_t rows, cols;
+    const float* W;
+    int64_t ld;
+    float* scale;
+};
+struct QrScale {
+    typedef QrScaleArgs Args;
+    static constexpr int NTH = 1024, WPE = 0;
+    static __device__ void run(const QrScaleArgs& a, int, int)
+    {
+        __shared__ float red[16];
+        float mx = 0.0f;
+        bool bad = false;
+        for (int64_t j = 0; j < a.cols; ++j)
+            for (int64_t i = threadIdx.x; i < a.rows; i += NTH) {
+                const float v = fabsf(a.W[i + j * a.ld]);
+                if (!(v <= 3.4e38f)) bad = true;   // inf or NaN
+                else mx = fmaxf(mx, v);
+            }
+        bad = __syncthreads_or(bad);
+        mx = wave_max(mx);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = 0.0f;
+            for (int w = 0; w < 16; ++w) m = fmaxf(m, red[w]);
+            int t = 0;
+            while (t < 31 && ((int64_t)1 << (2 * t)) < a.rows) ++t;
+            float c = 1.0f;
+            if (!bad && m > 0.0f) {
+                int E;
+                frexpf(m, &E);
+                c = ldexpf(1.0f, (14 - t) - E);
+            }
+            a.scale[0] = c;
+        }
+    }
+};
+
 struct RoundMatrixArgs {
     int64_t rows, cols;
     void* M;
     int64_t ld;
     int prec;
+    const float* scale;   // FP16: the QrScale factor applied before rounding
 };
 template <typename T>
 struct RoundMatrix {
@@ -622,7 +671,7 @@ __device__ void RoundMatrix<T>::run(const RoundMatrixArgs& a, int bx, int)
     const int64_t i = idx % rows, j = idx / rows;
     float v = (float)M[i + j * ld];
     if (prec == PNE_PREC_BF16) v = __uint_as_float((uint32_t)f32_to_bf16_bits(v) << 16);
-    else if (prec == PNE_PREC_FP16) v = (float)__builtin_bit_cast(_Float16, f32_to_f16_bits(v));
+    else if (prec == PNE_PREC_FP16) v = (float)__builtin_bit_cast(_Float16, f32_to_f16_bits(v * a.scale[0]));
     M[i + j * ld] = (T)v;
 }
 
@@ -635,6 +684,7 @@ struct ExtractRArgs {
     int prec;
     double* R;
     int64_t ldr;
+    const float* scale;   // FP16: divided out after the rounding (exact)
 };
 template <typename T>
 struct ExtractR {
@@ -659,14 +709,16 @@ __device__ void ExtractR<T>::run(const ExtractRArgs& a, int bx, int)
         } else {
             float f = W[i + j * ldw];
             if (prec == PNE_PREC_BF16) f = __uint_as_float((uint32_t)f32_to_bf16_bits(f) << 16);
-            else if (prec == PNE_PREC_FP16) f = (float)__builtin_bit_cast(_Float16, f32_to_f16_bits(f));
             v = (double)f;
+            if (prec == PNE_PREC_FP16)
+                v = (double)(float)__builtin_bit_cast(_Float16, f32_to_f16_bits(f)) / (double)a.scale[0];
         }
     }
     R[i + j * ldr] = v;
 }
 
-// First zero on the diagonal of R -> *info = 1000 + k + 1 (if no earlier failure).
+// First zero or non-finite diagonal entry of R -> *info = 1000 + k + 1 (if no
+// earlier failure).
 struct RDiagCheck {
     struct Args {
         int64_t n;
@@ -685,7 +737,7 @@ __device__ void RDiagCheck::run(const Args& a, int, int)
     __shared__ int64_t wmin[16];
     int64_t mine = n;
     for (int64_t k = threadIdx.x; k < n; k += 1024)
-        if (R[k + k * ldr] == 0.0 && k < mine) mine = k;
+        if ((R[k + k * ldr] == 0.0 || !isfinite(R[k + k * ldr])) && k < mine) mine = k;
     mine = -wave_max(-mine);
     if ((threadIdx.x & 63) == 0) wmin[threadIdx.x >> 6] = mine;
     __syncthreads();
@@ -727,6 +779,7 @@ static size_t qr_bytes(int64_t s, int64_t n)
     ar.take<T>((size_t)s * nb);          // V
     ar.take<T>((size_t)nb * nb);         // T
     ar.take<T>((size_t)ceil_div(s, QS_ROWS) * n * nb);   // chunk partials of V^T W
+    ar.take<float>(4);                                    // FP16 input scale
     return ar.used;
 }
 
@@ -778,10 +831,12 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
     T* V = ar.take<T>((size_t)s * NBv);
     T* Tm = ar.take<T>((size_t)NBv * NBv);
     T* Pq = ar.take<T>((size_t)ceil_div(s, QS_ROWS) * n * NBv);
+    float* qscale = ar.take<float>(4);
     ex.stage(ST_QR_ROUND);
     if constexpr (sizeof(T) == 4) {
+        if (prec == PNE_PREC_FP16) launch<QrScale>(ex, 1, 1, QrScaleArgs{s, n, (const float*)W, ldw, qscale});
         if (prec == PNE_PREC_BF16 || prec == PNE_PREC_FP16)
-            launch<RoundMatrix<T>>(ex, ceil_div(s * n, 256), 1, RoundMatrixArgs{s, n, W, ldw, prec});
+            launch<RoundMatrix<T>>(ex, ceil_div(s * n, 256), 1, RoundMatrixArgs{s, n, W, ldw, prec, qscale});
     }
     ex.stage(ST_QR);
     int64_t c0 = 0;
@@ -816,7 +871,7 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
         c0 += w;
     }
     ex.stage(ST_QR_EXTRACT);
-    launch<ExtractR<T>>(ex, ceil_div(n * n, 256), 1, ExtractRArgs{n, W, ldw, prec, R, ldr});
+    launch<ExtractR<T>>(ex, ceil_div(n * n, 256), 1, ExtractRArgs{n, W, ldw, prec, R, ldr, qscale});
     launch<RDiagCheck>(ex, 1, 1, RDiagCheck::Args{n, R, ldr, info});
     return launch_status(ex);
 }

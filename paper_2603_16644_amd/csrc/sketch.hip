@@ -1,4 +1,4 @@
-// Sketch A_s = Omega A (Algorithm 1, "Sketch"; Section 5.2), Omega an
+// Sketch A_s = Omega A (Algorithm 1, "Sketch"; Section 6.2), Omega an
 // s x m Gaussian matrix with N(0, 1/s) entries drawn from the counter-based
 // generator in philox.h.
 //

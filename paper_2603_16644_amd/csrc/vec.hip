@@ -79,15 +79,22 @@ void transpose_dinv(Exec& ex, int64_t n, const double* D, double* Dt)
 // forms x_b = D_b (c_b - sum), publishes x_b and raises its own flag.
 // flags[0] is the ticket counter and flags[1 + b] the flag of block b; all
 // must be zero at launch.  Waits are bounded: a flag that is not raised
-// within about 2^24 polls is passed over (the result is then invalid, but
-// the kernel ends).
+// within about 2^24 polls is passed over so that the kernel ends; the
+// result is then invalid and the info word receives 4000 + k + 1 (k the
+// 0-based block waited for) unless an earlier failure is already recorded,
+// which also makes the solver fill x with NaN.
 constexpr int LB_THREADS = 256;
 
-__device__ __forceinline__ void lb_wait(int32_t* f)
+__device__ __forceinline__ void lb_wait(int32_t* f, int32_t* info, int64_t block)
 {
     for (uint32_t it = 0; it < (1u << 24); ++it) {
         if (__hip_atomic_load(f, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != 0) return;
         __builtin_amdgcn_s_sleep(1);
+    }
+    if (info) {
+        int32_t expected = 0;
+        __hip_atomic_compare_exchange_strong(info, &expected, 4000 + (int32_t)block + 1, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
@@ -104,6 +111,7 @@ struct LBSolve {
     double* x;
     int32_t* flags;            // flags[1 + b]: block b of x is final
     const int32_t* rhs_flags;  // null, or the flags of the solve that writes rhs
+    int32_t* info;             // status word for a wait that gives up (may be null)
 };
 
 // Work-group of the t-th block (in dependency order) of solve sv.
@@ -123,7 +131,7 @@ __device__ void lb_solve_block(const LBSolve& sv, int64_t t)
         const int64_t j = sv.lower ? q : nb - 1 - q;
         const int64_t c0 = j * TB;
         const int jw = (int)((n - c0 < TB) ? n - c0 : TB);
-        if (tid == 0) lb_wait(sv.flags + 1 + j);
+        if (tid == 0) lb_wait(sv.flags + 1 + j, sv.info, j);
         __syncthreads();
         if (tid < TB)
             xs[tid] = (tid < jw) ? __hip_atomic_load(sv.x + c0 + tid, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
@@ -142,7 +150,7 @@ __device__ void lb_solve_block(const LBSolve& sv, int64_t t)
         __syncthreads();
     }
     red[p][i] = s;
-    if (sv.rhs_flags && tid == 0) lb_wait(const_cast<int32_t*>(sv.rhs_flags) + 1 + b);
+    if (sv.rhs_flags && tid == 0) lb_wait(const_cast<int32_t*>(sv.rhs_flags) + 1 + b, sv.info, b);
     __syncthreads();
     if (tid < TB) {
         double rv = 0.0;
@@ -183,6 +191,7 @@ struct TrsvLB {
         const double* D;
         double* x;          // in: right-hand side; out: solution
         int32_t* flags;     // 1 + ceil(n / 64) words, zero at launch
+        int32_t* info;      // status word (may be null)
     };
     static constexpr int NTH = LB_THREADS, WPE = 0;
     static __device__ void run(const Args& a, int, int)
@@ -190,7 +199,7 @@ struct TrsvLB {
         __shared__ int32_t tk;
         if (threadIdx.x == 0) tk = atomicAdd(a.flags, 1);
         __syncthreads();
-        lb_solve_block(LBSolve{a.n, a.M, a.ld, a.lower, a.D, a.x, a.x, a.flags, nullptr}, tk);
+        lb_solve_block(LBSolve{a.n, a.M, a.ld, a.lower, a.D, a.x, a.x, a.flags, nullptr, a.info}, tk);
     }
 };
 
@@ -218,9 +227,9 @@ struct TrsvLB2 {
 size_t lb_flag_words(int64_t n) { return (size_t)((n + TB - 1) / TB) + 1; }
 
 static void trsv_lb(Exec& ex, int64_t n, const double* M, int64_t ld, int lower, const double* D, double* x,
-                    int32_t* flags)
+                    int32_t* flags, int32_t* info)
 {
-    launch<TrsvLB>(ex, (n + TB - 1) / TB, 1, TrsvLB::Args{n, M, ld, lower, D, x, flags});
+    launch<TrsvLB>(ex, (n + TB - 1) / TB, 1, TrsvLB::Args{n, M, ld, lower, D, x, flags, info});
 }
 
 // Row exchanges of the LU pivots applied to x in order (one work-group).
@@ -239,7 +248,7 @@ struct ApplyPivots {
         if (threadIdx.x == 0)
             for (int64_t k = 0; k < a.n; ++k) {
                 const int64_t p = a.piv[k];
-                if (p != k) { const double t = xs[k]; xs[k] = xs[p]; xs[p] = t; }
+                if (p != k && p >= 0 && p < a.n) { const double t = xs[k]; xs[k] = xs[p]; xs[p] = t; }
             }
         __syncthreads();
         for (int64_t k = threadIdx.x; k < a.n; k += NTH) a.x[k] = xs[k];
@@ -248,28 +257,28 @@ struct ApplyPivots {
 
 void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const double* DL, const double* Lt,
                   const double* DLt, const double* R, int64_t ldr, const double* DR, const double* c, double* x,
-                  double* y, int32_t* flags)
+                  double* y, int32_t* flags, int32_t* info)
 {
     const int64_t fw = (int64_t)lb_flag_words(n);
     zero_i32(ex, 3 * fw, flags);
     if (c != x) copy_f64(ex, n, 1, c, n, x, n);
-    trsv_lb(ex, n, L, ldl, 1, DL, x, flags);
+    trsv_lb(ex, n, L, ldl, 1, DL, x, flags, info);
     // L^T y = z into y, then R x = y, in one launch (both backward)
-    const LBSolve s1{n, Lt, n, 0, DLt, x, y, flags + fw, nullptr};
-    const LBSolve s2{n, R, ldr, 0, DR, y, x, flags + 2 * fw, flags + fw};
+    const LBSolve s1{n, Lt, n, 0, DLt, x, y, flags + fw, nullptr, info};
+    const LBSolve s2{n, R, ldr, 0, DR, y, x, flags + 2 * fw, flags + fw, info};
     const int64_t nb = (n + TB - 1) / TB;
     launch<TrsvLB2>(ex, 2 * nb, 1, TrsvLB2::Args{s1, s2, flags + fw});
 }
 
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
-                 const double* DU, const double* c, double* x, int32_t* flags)
+                 const double* DU, const double* c, double* x, int32_t* flags, int32_t* info)
 {
     const int64_t fw = (int64_t)lb_flag_words(n);
     zero_i32(ex, 2 * fw, flags);
     if (c != x) copy_f64(ex, n, 1, c, n, x, n);
     launch<ApplyPivots>(ex, 1, 1, ApplyPivots::Args{n, piv, x});
-    trsv_lb(ex, n, LU, ld, 1, DL, x, flags);
-    trsv_lb(ex, n, LU, ld, 0, DU, x, flags + fw);
+    trsv_lb(ex, n, LU, ld, 1, DL, x, flags, info);
+    trsv_lb(ex, n, LU, ld, 0, DU, x, flags + fw, info);
 }
 
 // r = b - A x.  A work-group takes 64 rows; its four wavefronts take the
@@ -472,5 +481,23 @@ struct ZeroI32 {
     }
 };
 void zero_i32(Exec& ex, int64_t n, int32_t* p) { launch<ZeroI32>(ex, ceil_div(n, 256), 1, ZeroI32::Args{n, p}); }
+
+struct CopyI32 {
+    struct Args {
+        int64_t n;
+        const int32_t* s;
+        int32_t* d;
+    };
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int)
+    {
+        const int64_t i = (int64_t)bx * 256 + threadIdx.x;
+        if (i < a.n) a.d[i] = a.s[i];
+    }
+};
+void copy_i32(Exec& ex, int64_t n, const int32_t* src, int32_t* dst)
+{
+    launch<CopyI32>(ex, ceil_div(n, 256), 1, CopyI32::Args{n, src, dst});
+}
 
 }  // namespace pne

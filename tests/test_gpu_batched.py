@@ -130,3 +130,39 @@ def test_batch512_known_solutions(pne):
         if not e <= 10 * bound:
             bad.append((i, p.m, p.n, p.kappa, p.rho, e, bound))
     assert not bad, bad[:10]
+
+
+def test_batch512_sampled_members_within_qr_error(pne):
+    """Sixteen members of the 512-problem batch, generated on the CPU as the
+    stored oracle QR errors were (tests/golden/err_qr_full_size.txt, written by
+    tests/golden/make_err_qr.py) and solved together in one batched call with
+    their member indices as problem ids: members never interact and every
+    member's products are cut into the same fixed row chunks in any batch, so
+    each result is the one the member gets inside the full batch.  Each is
+    within 10x the oracle QR solver's own error."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "err_qr_full_size.txt")
+    rows = [l.split() for l in open(path) if l.startswith("batch512_member")]
+    assert len(rows) == 16
+    shapes = draw_batch_shapes(512, 0)
+    probs, errs, ids = [], [], []
+    for t in rows:
+        i = int(t[0][len("batch512_member"):])
+        m, n, k, r = shapes[i]
+        assert (m, n, int(t[5])) == (int(t[1]), int(t[2]), 40000 + i)
+        probs.append(make_problem(m, n, k, r, seed=40000 + i, device="cpu"))
+        errs.append(float(t[6]))
+        ids.append(i)
+    A, b, x, descs = pack(probs)
+    for d, i in zip(descs, ids):
+        d["problem_id"] = i
+    o = pne.make_opts(seed=0, sketch_prec="bf16", qr_prec="fp32", refine_steps=3)
+    info = host(pne.pne_solve_batched(A, b, x, descs, opts=o))
+    assert np.all(info == 0)
+    xb = host(x)
+    bad = []
+    for p, d, e_qr, i in zip(probs, descs, errs, ids):
+        e = relerr(xb[d["x_offset"]:d["x_offset"] + p.n], p.numpy_x_star())
+        if not e <= 10 * e_qr:
+            bad.append((i, p.m, p.n, p.kappa, p.rho, e, e_qr))
+    assert not bad, bad

@@ -81,7 +81,7 @@ def test_1e6x2000_sampled_sketch_fp64(pne, orc, p3):
 
 def test_1e6x2000_auto_picks_double_and_is_accurate(pne, p3):
     """kappa = 1e10: the FP32 Gram of the estimate breaks down, so the pick is
-    double (Section 6.4); the solution then meets the least-squares bound."""
+    double (Section 7.4); the solution then meets the least-squares bound."""
     o = pne.make_opts(s=6000, seed=3, sketch_prec="auto", qr_prec="auto", refine_steps=1)
     x, info, meta = pne.pne_solve(p3.A, p3.b, opts=o)
     assert int(host(info)[0]) == 0

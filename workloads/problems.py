@@ -1,7 +1,7 @@
 """Exact least-squares problems A = U diag(sigma) V^T, b = A x_* + r.
 
 The construction follows the paper's recipe for "exact" least-squares
-problems (Section 6.1, Algorithm 2): an orthonormal basis U of range(A), a
+problems (Section 7, Algorithm 2): an orthonormal basis U of range(A), a
 prescribed condition number, a known solution x_* and a residual r that is
 orthogonal to range(A) and has a prescribed relative size
 
