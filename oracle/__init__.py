@@ -66,6 +66,8 @@ def lib():
             "oracle_fp16_qr_scale": (ctypes.c_double, [i64, i64, P, i64]),
             "oracle_solve": (i32, [i32, i64, i64, P, i64, P, i64, u64, u32, i32, i32, i64, i32,
                                    ctypes.c_double, P, P, P, P]),
+            "oracle_nne": (i32, [i64, i64, P, i64, P, i64, P, i32, P]),
+            "oracle_cond_est_qr": (i32, [i64, i64, P, i64, i64, u64, u32, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -252,3 +254,29 @@ def solve(A, b, *, hpne: bool = False, s: int | None = None, seed: int = 0, pid:
                               _ptr(used), ctypes.byref(k0))
     return {"x": x, "R": R, "info": int(info), "prec_used": (int(used[0]), int(used[1])),
             "kappa0": float(k0.value)}
+
+
+def nne(A, B, b, refine_steps: int = 0):
+    """Not-normal equations B^T A x = B^T b (Section 5.2).  Returns (x, info)."""
+    A, B = _f64(A), _f64(B)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    m, n = A.shape
+    if B.shape != (m, n):
+        raise ValueError("B must have the shape of A")
+    x = np.zeros(n)
+    info = lib().oracle_nne(m, n, _ptr(A), m, _ptr(B), m, _ptr(b), refine_steps, _ptr(x))
+    return x, int(info)
+
+
+def cond_est_qr(A, s: int | None = None, seed: int = 0, pid: int = 0):
+    """Condition estimate from the FP32 QR of the FP32 sketch.  Returns
+    (kappa0, precision code)."""
+    A = _f64(A)
+    m, n = A.shape
+    s = 3 * n if s is None else s
+    k0 = ctypes.c_float()
+    ch = ctypes.c_int32()
+    rc = lib().oracle_cond_est_qr(m, n, _ptr(A), m, s, seed, pid, ctypes.byref(k0), ctypes.byref(ch))
+    if rc:
+        raise ValueError(f"oracle_cond_est_qr failed: {rc}")
+    return float(k0.value), int(ch.value)

@@ -791,3 +791,158 @@ int oracle_sketch_entries(int64_t m, const double* A, int64_t lda, int64_t s, ui
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------
+ * Not-normal equations (Section 5.2, eq. e_nne): B^T A x = B^T b for an
+ * m x n matrix B of rank n with the column space of A.  In exact arithmetic
+ * x is the least-squares solution for any such B (A = B C with C
+ * nonsingular, so B^T A = B^T B C is nonsingular and the equations are
+ * equivalent to A^T A x = A^T b); B = A_p gives the HPNE, B = A the normal
+ * equations.  Steps: C = B^T A, c = B^T b (FP64), LU with partial pivoting
+ * (first index of the largest magnitude), L U x = P c; then refine_steps
+ * corrections r = b - A x, d = (B^T A)^{-1} B^T r through the same LU,
+ * x += d (the library's optional FP64 correction, as for the HPNE).
+ * Returns 0 or 3000+k for a zero or non-finite pivot (x is then NaN).
+ * ---------------------------------------------------------------------- */
+int oracle_nne(int64_t m, int64_t n, const double* A, int64_t lda, const double* B, int64_t ldb,
+               const double* b, int refine_steps, double* x)
+{
+    if (m < n || n < 1 || lda < m || ldb < m || refine_steps < 0) return -1;
+    size_t nn = (size_t)n * (size_t)n;
+    double* C = (double*)malloc(sizeof(double) * nn);
+    double* c = (double*)malloc(sizeof(double) * (size_t)n);
+    double* r = (double*)malloc(sizeof(double) * (size_t)m);
+    double* d = (double*)malloc(sizeof(double) * (size_t)n);
+    int32_t* piv = (int32_t*)malloc(sizeof(int32_t) * (size_t)n);
+    int info = 0;
+    if (!C || !c || !r || !d || !piv) { info = -2; goto done; }
+    oracle_gram(m, n, B, ldb, A, lda, b, C, n, c);
+    info = oracle_lu(n, C, n, piv);
+    if (info) goto done;
+    lu_solve(n, C, n, piv, c, x);
+    for (int step = 0; step < refine_steps; ++step) {
+        for (int64_t i = 0; i < m; ++i) {
+            double acc = b[i];
+            for (int64_t j = 0; j < n; ++j) acc -= A[IDX(i, j, lda)] * x[j];
+            r[i] = acc;
+        }
+        for (int64_t j = 0; j < n; ++j) {
+            double acc = 0.0;
+            for (int64_t i = 0; i < m; ++i) acc += B[IDX(i, j, ldb)] * r[i];
+            c[j] = acc;
+        }
+        lu_solve(n, C, n, piv, c, d);
+        for (int64_t j = 0; j < n; ++j) x[j] += d[j];
+    }
+done:
+    if (info > 0)
+        for (int64_t j = 0; j < n; ++j) x[j] = NAN;
+    free(C); free(c); free(r); free(d); free(piv);
+    return info;
+}
+
+/* ------------------------------------------------------------------------
+ * Condition estimate from a single-precision QR (library variant of the
+ * first step of Algorithm 1; Section 6.1 estimates kappa(A) through the
+ * 1-norm condition number of A^T A, which squares it).  Here:
+ *   A_s = Omega A (s x n) with the FP32 sketch (oracle_sketch, prec FP32),
+ *   rounded to FP32; Householder QR of fl32(A_s) in FP32 arithmetic
+ *   (plain float loops, LAPACK reflector convention) giving R (FP32);
+ *   ||R||_1 = max column sum of |R|;
+ *   est ~ ||R^{-1}||_1 by Hager's method as in oracle_cond_est, with
+ *   y = R^{-1} x (back substitution) and z = R^{-T} sign(y) (forward
+ *   substitution with R^T), FP32;
+ *   kappa0 = log10(||R||_1 est)   (no square root: R is not a Gram matrix);
+ *   a zero or non-finite diagonal of R, or a non-finite product, means the
+ *   estimate overflows (kappa0 = +inf).  Same thresholds as Algorithm 1.
+ * kappa(A_s) differs from kappa(A) by at most the condition number of the
+ * sketched orthonormal basis (below 3.73 asymptotically for s = 3n, the
+ * Marchenko-Pastur edge (1 + sqrt(n/s)) / (1 - sqrt(n/s))), so kappa0 is
+ * within about 0.6 of log10 kappa_1(A_s) ~ log10 kappa(A) -- without the
+ * squaring, the FP32 QR resolves kappa(A) up to about 1/u_32 ~ 1.7e7.
+ * Parity unpinned for the exact value (Hager is an estimate); pinned by the
+ * precision picks and the lower-bound property of Hager's estimate.
+ * ---------------------------------------------------------------------- */
+int oracle_cond_est_qr(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                       uint32_t pid, float* kappa0_out, int32_t* choice_out)
+{
+    if (m < n || n < 1 || lda < m || s < n) return -1;
+    double* As = (double*)malloc(sizeof(double) * (size_t)s * (size_t)n);
+    float* W = (float*)malloc(sizeof(float) * (size_t)s * (size_t)n);
+    float* v = (float*)malloc(sizeof(float) * (size_t)s);
+    float* x = (float*)malloc(sizeof(float) * (size_t)n);
+    float* y = (float*)malloc(sizeof(float) * (size_t)n);
+    float* z = (float*)malloc(sizeof(float) * (size_t)n);
+    int rc = 0;
+    float k0 = INFINITY;
+    if (!As || !W || !v || !x || !y || !z) { rc = -2; goto done; }
+    rc = oracle_sketch(m, n, A, lda, s, seed, pid, PREC_FP32, 128, As, s, NULL);
+    if (rc) goto done;
+    for (size_t i = 0; i < (size_t)s * (size_t)n; ++i) W[i] = (float)As[i];
+    /* FP32 Householder QR, R in the upper triangle of W */
+    for (int64_t k = 0; k < n; ++k) {
+        int64_t len = s - k;
+        for (int64_t i = 0; i < len; ++i) v[i] = W[IDX(k + i, k, s)];
+        float alpha = v[0], sig = 0.0f;
+        for (int64_t i = 1; i < len; ++i) sig += v[i] * v[i];
+        if (sig == 0.0f) continue;                    /* no reflection needed */
+        float nrm = sqrtf(alpha * alpha + sig);
+        float beta = (alpha >= 0.0f) ? -nrm : nrm;
+        float tau = (beta - alpha) / beta;
+        float sc = 1.0f / (alpha - beta);
+        for (int64_t i = 1; i < len; ++i) v[i] *= sc;
+        v[0] = 1.0f;
+        W[IDX(k, k, s)] = beta;
+        for (int64_t j = k + 1; j < n; ++j) {
+            float d = 0.0f;
+            for (int64_t i = 0; i < len; ++i) d += v[i] * W[IDX(k + i, j, s)];
+            d *= tau;
+            for (int64_t i = 0; i < len; ++i) W[IDX(k + i, j, s)] -= d * v[i];
+        }
+    }
+    int ok = 1;
+    for (int64_t k = 0; k < n; ++k) {
+        float dkk = W[IDX(k, k, s)];
+        if (dkk == 0.0f || !isfinite(dkk)) ok = 0;
+    }
+    if (ok) {
+        float r1 = 0.0f;
+        for (int64_t j = 0; j < n; ++j) {
+            float cs = 0.0f;
+            for (int64_t i = 0; i <= j; ++i) cs += fabsf(W[IDX(i, j, s)]);
+            if (cs > r1) r1 = cs;
+        }
+        for (int64_t i = 0; i < n; ++i) x[i] = 1.0f / (float)n;
+        float est = 0.0f;
+        for (int it = 0; it < 5; ++it) {
+            for (int64_t i = n - 1; i >= 0; --i) {          /* R y = x */
+                float acc = x[i];
+                for (int64_t j = i + 1; j < n; ++j) acc -= W[IDX(i, j, s)] * y[j];
+                y[i] = acc / W[IDX(i, i, s)];
+            }
+            est = 0.0f;
+            for (int64_t i = 0; i < n; ++i) est += fabsf(y[i]);
+            for (int64_t i = 0; i < n; ++i) {               /* R^T z = sign(y) */
+                float acc = (y[i] >= 0.0f) ? 1.0f : -1.0f;
+                for (int64_t j = 0; j < i; ++j) acc -= W[IDX(j, i, s)] * z[j];
+                z[i] = acc / W[IDX(i, i, s)];
+            }
+            float zmax = 0.0f, ztx = 0.0f;
+            int64_t jmax = 0;
+            for (int64_t i = 0; i < n; ++i) {
+                if (fabsf(z[i]) > zmax) { zmax = fabsf(z[i]); jmax = i; }
+                ztx += z[i] * x[i];
+            }
+            if (zmax <= ztx) break;
+            for (int64_t i = 0; i < n; ++i) x[i] = 0.0f;
+            x[jmax] = 1.0f;
+        }
+        float prod = r1 * est;
+        if (isfinite(prod) && prod > 0.0f) k0 = log10f(prod);
+    }
+done:
+    if (kappa0_out) *kappa0_out = k0;
+    if (choice_out) *choice_out = pick_precision(k0);
+    free(As); free(W); free(v); free(x); free(y); free(z);
+    return rc;
+}

@@ -303,7 +303,11 @@ def test_auto_picks_single_precision(pne, orc):
     """kappa = 3.5e3, n = 400: the estimate lands in the single-precision
     band (4 <= kappa0 <= 8), on the GPU as in the oracle.  The band is
     narrow for an FP32 Gram (its Cholesky breaks down from kappa ~ 4e3 on,
-    which selects double), so the case sits just inside it."""
+    which selects double), so the case sits just inside it.  There
+    kappa(A)^2 u_32 is about 0.7: the rounding error of the FP32 Gram is of
+    the size of its smallest eigenvalue, so the estimate depends on the
+    summation order (MFMA blocks on the GPU, sequential sums in the oracle)
+    by a few tenths in log10.  The pick is what must agree."""
     p = make_problem(4000, 400, 3.5e3, 1e-6, seed=1014)
     A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
     k0o, _, cho = orc.cond_est(A)
@@ -311,7 +315,7 @@ def test_auto_picks_single_precision(pne, orc):
     o = pne.make_opts(seed=1, sketch_prec="auto", qr_prec="auto", refine_steps=1)
     x, info, meta = pne.pne_solve(dev(A), torch.from_numpy(b).cuda(), opts=o)
     assert meta["sketch_prec"] == "fp32" and meta["qr_prec"] == "fp32"
-    assert abs(meta["kappa0"] - k0o) < 0.1
+    assert 4.0 <= meta["kappa0"] <= 8.0 and abs(meta["kappa0"] - k0o) < 0.6
     assert int(host(info)[0]) == 0
     assert relerr(host(x), xs) <= 10 * relerr(orc.qr_ls(A, b), xs)
 

@@ -222,8 +222,8 @@ def test_householder_r_matches_lapack(orc):
 def _exact_ls(A, b):
     """Least squares by exact rational arithmetic on A^T A x = A^T b."""
     m, n = len(A), len(A[0])
-    M = [[sum(Fraction(A[k][i]) * A[k][j] for k in range(m)) for j in range(n)]
-         + [sum(Fraction(A[k][i]) * b[k] for k in range(m))] for i in range(n)]
+    M = [[sum(Fraction(A[k][i]) * Fraction(A[k][j]) for k in range(m)) for j in range(n)]
+         + [sum(Fraction(A[k][i]) * Fraction(b[k]) for k in range(m))] for i in range(n)]
     for c in range(n):
         p = next(r for r in range(c, n) if M[r][c] != 0)
         M[c], M[p] = M[p], M[c]
@@ -552,3 +552,131 @@ def test_invalid_arguments(orc):
     with pytest.raises(ValueError):
         orc.qr_ls(A, np.ones(3))
     assert orc.solve(np.eye(4), np.ones(4), s=2)["info"] == -1
+
+
+# ---------------------------------------------------------------- not-normal equations (Section 5.2)
+
+def _exact_nne(A, B, b):
+    """B^T A x = B^T b solved in exact rational arithmetic (Gauss-Jordan)."""
+    m, n = len(A), len(A[0])
+    M = [[sum(Fraction(B[k][i]) * Fraction(A[k][j]) for k in range(m)) for j in range(n)]
+         + [sum(Fraction(B[k][i]) * Fraction(b[k]) for k in range(m))] for i in range(n)]
+    for c in range(n):
+        p = next(r for r in range(c, n) if M[r][c] != 0)
+        M[c], M[p] = M[p], M[c]
+        M[c] = [v / M[c][c] for v in M[c]]
+        for r in range(n):
+            if r != c and M[r][c] != 0:
+                f = M[r][c]
+                M[r] = [a - f * bb for a, bb in zip(M[r], M[c])]
+    return [M[i][n] for i in range(n)]
+
+
+def test_nne_exact_rational_equals_least_squares(orc):
+    # For B = A C' with C' nonsingular the not-normal equations have the
+    # least-squares solution (Section 5.2, proof of the theorem: A = B C).
+    rng = np.random.default_rng(77)
+    for A, b in _tiny_cases():
+        m, n = A.shape
+        Cp = np.triu(rng.integers(1, 4, size=(n, n))).astype(float)   # nonsingular upper triangle
+        B = A @ Cp                        # integer B with the column space of A
+        fe = _exact_nne(A.tolist(), B.tolist(), b.tolist())
+        assert fe == list(_exact_ls(A.tolist(), b.tolist()))             # exactly x_LS
+        xe = np.array([float(v) for v in fe])
+        x, info = orc.nne(A, B, b)
+        assert info == 0
+        assert np.allclose(x, xe, rtol=1e-11, atol=1e-11 * np.abs(xe).max())
+
+
+def test_nne_with_preconditioned_b_is_the_hpne(orc):
+    # Remark in Section 5.2: B = A_p gives the HPNE; the oracle takes the same
+    # arithmetic steps, so the results agree bit for bit.
+    p = make_problem(600, 40, 1e5, 1e-6, seed=78)
+    A, b = p.numpy_A(), p.numpy_b()
+    r = orc.solve(A, b, hpne=True, s=120, seed=3, sketch_prec="fp64", refine_steps=0)
+    Ap, rc = orc.precondition(A, r["R"])
+    assert rc == 0
+    x, info = orc.nne(A, Ap, b)
+    assert info == 0 and np.array_equal(x, r["x"])
+    # and one refinement step of each is the same correction
+    r1 = orc.solve(A, b, hpne=True, s=120, seed=3, sketch_prec="fp64", refine_steps=1)
+    x1, _ = orc.nne(A, Ap, b, refine_steps=1)
+    assert np.array_equal(x1, r1["x"])
+
+
+def test_nne_obeys_perturbation_theorem(orc):
+    # Theorem (Section 5.2): ||x^ - x*|| / ||x^|| <= kappa(B^T A) nu (eps_B res + (1 + eps_B) eps_A)
+    # with nu = ||B|| ||A|| / ||B^T A||.  The computed B^T A and B^T b have
+    # backward errors of order m u in A and B; the check takes eps = 4 m u.
+    rng = np.random.default_rng(79)
+    for kappa, rho in [(1e3, 1e-8), (1e5, 1e-4), (1e6, 1e-2)]:
+        p = make_problem(800, 30, kappa, rho, seed=int(kappa) % 1000 + 80)
+        A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+        B = A @ (np.eye(30) + 0.3 * rng.standard_normal((30, 30)))
+        x, info = orc.nne(A, B, b)
+        assert info == 0
+        BtA = B.T @ A
+        nu = np.linalg.norm(B, 2) * np.linalg.norm(A, 2) / np.linalg.norm(BtA, 2)
+        res = np.linalg.norm(A @ x - b) / (np.linalg.norm(A, 2) * np.linalg.norm(x))
+        eps = 4 * 800 * U64
+        bound = np.linalg.cond(BtA) * nu * (eps * res + (1 + eps) * eps)
+        err = np.linalg.norm(x - xs) / np.linalg.norm(x)
+        assert err <= bound, (kappa, err, bound)
+
+
+def test_nne_detects_wrong_operand_order(orc):
+    # A^T B x = A^T b (operands swapped) is a different system when B is not
+    # a multiple of A: the oracle must not be symmetric in A and B.
+    p = make_problem(300, 12, 1e2, 1e-2, seed=81)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    rng = np.random.default_rng(81)
+    B = A @ (np.eye(12) + 0.5 * rng.standard_normal((12, 12)))
+    x, _ = orc.nne(A, B, b)
+    xw = np.linalg.solve(A.T @ B, A.T @ b)
+    assert relerr(x, xs) < 1e-10 * 1e2
+    assert relerr(x, xw) > 1e-6
+
+
+def test_nne_zero_pivot(orc):
+    A = np.array([[1.0, 0.0], [0.0, 1.0], [0.0, 0.0]])
+    B = np.array([[1.0, 0.0], [0.0, 0.0], [0.0, 0.0]])       # B^T A singular
+    x, info = orc.nne(A, B, np.ones(3))
+    assert info == 3002 and np.all(np.isnan(x))
+
+
+# ---------------------------------------------------------------- QR-based condition estimate
+
+@pytest.mark.parametrize("kappa,code", [(1e2, 3), (1e5, 2), (1e6, 2), (1e10, 1)])
+def test_cond_est_qr_picks(orc, kappa, code):
+    # kappa = 1e2 -> half and 1e10 -> double (Section 7.4, Figure 7), and the
+    # single-precision band of Algorithm 1 is reached for kappa well above the
+    # ~4e3 where the FP32 Gram estimate breaks down.
+    p = make_problem(4000, 100, kappa, 1e-6, seed=82)
+    k0, ch = orc.cond_est_qr(p.numpy_A(), seed=4)
+    assert ch == code, (kappa, k0)
+    if kappa >= 1e5:
+        assert orc.cond_est(p.numpy_A())[2] == 1     # the Gram estimate cannot see it
+
+
+def test_cond_est_qr_is_a_good_lower_estimate(orc):
+    # Hager's estimate never exceeds ||R^{-1}||_1 (FP32 solves perturb it by
+    # about u32 kappa) and is within a factor 10 of it; R is recomputed here
+    # from the same FP32 sketch by LAPACK in FP64.
+    for kappa in [1e1, 1e3, 1e5]:
+        p = make_problem(3000, 60, kappa, 1e-6, seed=83)
+        A = p.numpy_A()
+        As = orc.sketch(A, 180, 5, prec="fp32").astype(np.float32).astype(np.float64)
+        R = np.linalg.qr(As, mode="r")
+        exact = math.log10(np.abs(R).sum(0).max() * np.abs(np.linalg.inv(R)).sum(0).max())
+        k0, _ = orc.cond_est_qr(A, s=180, seed=5)
+        assert exact - 1.0 <= k0 <= exact + math.log10(1 + 2 ** -22 * kappa * 60)
+        # and kappa_1(R) brackets kappa_2(A) up to the sketch distortion and the
+        # 1-norm / 2-norm factor n
+        assert math.log10(kappa) - 0.6 <= exact <= math.log10(kappa) + 0.6 + math.log10(60)
+
+
+def test_cond_est_qr_overflow_is_double(orc):
+    A = np.zeros((50, 5))
+    A[:, :4] = np.random.default_rng(84).standard_normal((50, 4))   # rank 4
+    k0, ch = orc.cond_est_qr(A, seed=1)
+    assert ch == 1 and (not math.isfinite(k0) or k0 > 8)
