@@ -199,6 +199,26 @@ int pne_profile_enable(int enable);
 int pne_profile_read(double* ms, int max_phases);
 const char* pne_profile_phase_name(int i);
 
+/* pne_solve_noalloc: pne_solve (hpne = 0) or hpne_solve (hpne = 1) for
+ * callers that cannot allocate device memory -- code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  Same arguments,
+ * kernels and results as those entry points, except that there is no dwork:
+ * the scratch space is one file-scope device array of PNE_NOALLOC_MAX_BYTES
+ * per GPU, which the library holds until the process ends.  Its address is
+ * looked up once per device on that device's first call.  A problem whose
+ * pne_workspace_size exceeds PNE_NOALLOC_MAX_BYTES returns PNE_EWORKSPACE
+ * before any device work.  The call itself allocates nothing (no hipMalloc,
+ * hipFree or allocating library routine).  All calls on one GPU share the
+ * array: two calls that overlap in time on one GPU (different streams or
+ * host threads without ordering) race and give undefined results; order
+ * them on one stream.  AUTO precision synchronises the stream once, as in
+ * pne_solve. */
+#define PNE_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+size_t pne_noalloc_max_bytes(void);
+pne_status pne_solve_noalloc(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
+                             double* dx, const pne_opts* opts, int hpne, int32_t* dinfo, pne_info* hinfo,
+                             pne_stream_t stream);
+
 /* Human-readable name of a status code (static string). */
 const char* pne_status_string(pne_status st);
 

@@ -5,7 +5,7 @@ The solver lives in the HIP library libpne.so behind the C ABI of
 include/pne.h; this package is its Python binding.
 """
 from ._lib import (PREC, Opts, PneError, cond_est, hpne_solve, lib, make_opts, pne_gram, pne_sketch,
-                   pne_solve, pne_solve_batched, sketch_precond)
+                   pne_solve, pne_solve_batched, pne_solve_noalloc, sketch_precond)
 
 __all__ = ["PREC", "Opts", "PneError", "cond_est", "hpne_solve", "lib", "make_opts", "pne_gram", "pne_sketch",
-           "pne_solve", "pne_solve_batched", "sketch_precond"]
+           "pne_solve", "pne_solve_batched", "pne_solve_noalloc", "sketch_precond"]

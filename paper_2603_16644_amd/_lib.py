@@ -27,7 +27,8 @@ EXPORTS = ["pne_default_opts", "pne_workspace_size", "pne_solve", "hpne_solve",
            "sketch_precond_workspace_size", "sketch_precond", "cond_est_workspace_size", "cond_est",
            "pne_sketch_workspace_size", "pne_sketch", "pne_batched_workspace_size",
            "pne_solve_batched", "pne_gram_workspace_size", "pne_gram", "pne_status_string",
-           "pne_profile_enable", "pne_profile_read", "pne_profile_phase_name"]
+           "pne_profile_enable", "pne_profile_read", "pne_profile_phase_name",
+           "pne_noalloc_max_bytes", "pne_solve_noalloc"]
 
 
 class PneError(RuntimeError):
@@ -87,6 +88,8 @@ def lib():
             "pne_profile_enable": (ctypes.c_int, [ctypes.c_int]),
             "pne_profile_read": (ctypes.c_int, [P, ctypes.c_int]),
             "pne_profile_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
+            "pne_noalloc_max_bytes": (sz, []),
+            "pne_solve_noalloc": (ctypes.c_int, [i64, i64, P, i64, P, P, OP, ctypes.c_int, P, P, P]),
         }
         for name, (res, args) in sigs.items():
             f = getattr(L, name)
@@ -176,6 +179,25 @@ def pne_solve(A, b, x=None, opts: Opts | None = None, stream=None, workspace=Non
 def hpne_solve(A, b, x=None, opts: Opts | None = None, stream=None, workspace=None):
     """HPNE solve (include/pne.h hpne_solve).  Returns (x, info tensor, meta dict)."""
     return _solve(True, A, b, x, opts, stream, workspace)
+
+
+def pne_solve_noalloc(A, b, x=None, opts: Opts | None = None, hpne: bool = False, stream=None):
+    """PNE/HPNE solve without a workspace (include/pne.h pne_solve_noalloc):
+    the library's per-GPU static scratch array replaces dwork.  Returns
+    (x, info tensor, meta dict)."""
+    m, n, lda = _colmajor(A)
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m:
+        raise ValueError("b must be a contiguous float64 vector of length m")
+    opts = opts or make_opts()
+    x = torch.empty(n, dtype=torch.float64, device=A.device) if x is None else x
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    hinfo = Info()
+    rc = lib().pne_solve_noalloc(m, n, A.data_ptr(), lda, b.data_ptr(), x.data_ptr(), ctypes.byref(opts),
+                                 int(hpne), info.data_ptr(), ctypes.byref(hinfo), _stream_ptr(stream))
+    _check("pne_solve_noalloc", rc)
+    meta = {"sketch_prec": PREC_NAME.get(hinfo.sketch_prec_used), "qr_prec": PREC_NAME.get(hinfo.qr_prec_used),
+            "kappa0": hinfo.kappa0, "refine_steps": hinfo.refine_steps_run}
+    return x, info, meta
 
 
 def sketch_precond(A, opts: Opts | None = None, stream=None, workspace=None):

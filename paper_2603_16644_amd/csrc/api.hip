@@ -494,6 +494,28 @@ pne_status solve_batched(int64_t batch, const pne_problem_desc* hd, const double
 
 }  // namespace
 
+namespace pne {
+
+// Workspace bytes of one PNE/HPNE solve (argument checks of solve_impl that
+// need no device pointers); used by the no-allocation entry point.
+pne_status solve_workspace(int hpne, int64_t m, int64_t n, int64_t lda, const pne_opts* o, size_t* need)
+{
+    pne_status chk = check_common(m, n, (const void*)1, lda, o);
+    if (chk) return chk;
+    if (hpne && !lu_supported(n)) return PNE_ENOTSUP;
+    *need = layout(make_problem(m, n, lda, o, hpne), nullptr, 0, nullptr, true);
+    return PNE_OK;
+}
+
+pne_status solve_entry(int hpne, int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
+                       double* dx, const pne_opts* o, void* dwork, size_t work_bytes, int32_t* dinfo,
+                       pne_info* hinfo, hipStream_t st)
+{
+    return solve_impl(hpne, m, n, dA, lda, db, dx, o, dwork, work_bytes, dinfo, hinfo, st);
+}
+
+}  // namespace pne
+
 extern "C" {
 
 void pne_default_opts(pne_opts* o)

@@ -154,4 +154,13 @@ size_t condest_workspace_bytes(int64_t m, int64_t n, int64_t kchunk_fixed = 0);
 int condest_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
                 int32_t* dchoice, void* work, size_t work_bytes);
 
+// ---------------------------------------------------------------- single solves (api.hip)
+// workspace bytes of one PNE (hpne = 0) / HPNE (hpne = 1) solve, after the
+// host-side argument checks of the solvers
+pne_status solve_workspace(int hpne, int64_t m, int64_t n, int64_t lda, const pne_opts* o, size_t* need);
+// pne_solve / hpne_solve on a given workspace
+pne_status solve_entry(int hpne, int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
+                       double* dx, const pne_opts* o, void* dwork, size_t work_bytes, int32_t* dinfo,
+                       pne_info* hinfo, hipStream_t st);
+
 }  // namespace pne

@@ -63,6 +63,12 @@ def test_host_argument_checks(pne):
     assert L.pne_solve(10**6, 5000, one, 10**6, one, one, by(o), one, 1 << 40, one, None, None) == -5
     assert L.cond_est(10, 20, one, 10, one, one, one, 1 << 20, None) == -1
     assert L.pne_status_string(-4) == b"workspace too small"
+    # the no-allocation entry point checks sizes against its static array first
+    assert L.pne_noalloc_max_bytes() == 64 << 20
+    assert L.pne_solve_noalloc(20000, 1000, one, 20000, one, one, by(o), 0, one, None, None) == -4
+    assert L.pne_solve_noalloc(1000, 100, None, 1000, one, one, by(o), 0, one, None, None) == -1
+    assert L.pne_solve_noalloc(1000, 100, one, 1000, one, one, by(o), 2, one, None, None) == -1
+    assert L.pne_solve_noalloc(100, 200, one, 100, one, one, by(o), 1, one, None, None) == -1
 
 
 def test_workspace_grows_with_problem(pne):
