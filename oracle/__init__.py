@@ -65,7 +65,12 @@ def lib():
             "oracle_sketch_entries": (i32, [i64, P, i64, i64, u64, u32, i32, i64, i64, P, P, P, P]),
             "oracle_fp16_qr_scale": (ctypes.c_double, [i64, i64, P, i64]),
             "oracle_solve": (i32, [i32, i64, i64, P, i64, P, i64, u64, u32, i32, i32, i64, i32,
-                                   ctypes.c_double, P, P, P, P]),
+                                   ctypes.c_double, i32, P, P, P, P]),
+            "oracle_next_smooth": (i64, [i64]),
+            "oracle_srft_sign": (i32, [u64, u32, i64]),
+            "oracle_srft_index": (i64, [u64, u32, i64, i64]),
+            "oracle_srft_sketch": (i32, [i64, i64, P, i64, i64, u64, u32, i32, P, i64]),
+            "oracle_srft_entries": (i32, [i64, P, i64, i64, u64, u32, i32, i64, P, P, P]),
             "oracle_nne": (i32, [i64, i64, P, i64, P, i64, P, i32, P]),
             "oracle_cond_est_qr": (i32, [i64, i64, P, i64, i64, u64, u32, P, P]),
         }
@@ -236,9 +241,12 @@ def cond_est(A, known_kappa: float = 0.0):
     return float(k0.value), float(k0n.value), int(ch.value)
 
 
+SKETCH_KIND = {"gaussian": 0, "srft": 1}
+
+
 def solve(A, b, *, hpne: bool = False, s: int | None = None, seed: int = 0, pid: int = 0,
           sketch_prec: str = "fp64", qr_prec: str | None = None, block_rows: int = 128,
-          refine_steps: int = 0, known_kappa: float = 0.0):
+          refine_steps: int = 0, known_kappa: float = 0.0, sketch_kind: str = "gaussian"):
     """Algorithm 1 (PNE or HPNE).  Returns dict(x, R, info, prec_used, kappa0)."""
     A = _f64(A)
     b = np.ascontiguousarray(b, dtype=np.float64)
@@ -250,7 +258,8 @@ def solve(A, b, *, hpne: bool = False, s: int | None = None, seed: int = 0, pid:
     used = np.zeros(2, dtype=np.int32)
     k0 = ctypes.c_float()
     info = lib().oracle_solve(int(hpne), m, n, _ptr(A), m, _ptr(b), s, seed, pid, PREC[sketch_prec],
-                              PREC[qr_prec], block_rows, refine_steps, known_kappa, _ptr(x), _ptr(R),
+                              PREC[qr_prec], block_rows, refine_steps, known_kappa, SKETCH_KIND[sketch_kind],
+                              _ptr(x), _ptr(R),
                               _ptr(used), ctypes.byref(k0))
     return {"x": x, "R": R, "info": int(info), "prec_used": (int(used[0]), int(used[1])),
             "kappa0": float(k0.value)}
@@ -280,3 +289,41 @@ def cond_est_qr(A, s: int | None = None, seed: int = 0, pid: int = 0):
     if rc:
         raise ValueError(f"oracle_cond_est_qr failed: {rc}")
     return float(k0.value), int(ch.value)
+
+
+def next_smooth(m: int) -> int:
+    """Smallest 7-smooth integer >= m (the padded length of the SRFT)."""
+    return int(lib().oracle_next_smooth(m))
+
+
+def srft_signs(seed: int, m: int, pid: int = 0) -> np.ndarray:
+    return np.array([lib().oracle_srft_sign(seed, pid, j) for j in range(m)], dtype=np.float64)
+
+
+def srft_indices(seed: int, s: int, mp: int, pid: int = 0) -> np.ndarray:
+    return np.array([lib().oracle_srft_index(seed, pid, i, mp) for i in range(s)], dtype=np.int64)
+
+
+def srft_sketch(A, s: int, seed: int, prec: str = "fp64", pid: int = 0) -> np.ndarray:
+    """A_s = (1/sqrt(s)) S H D A with the Hartley transform (Section 6.2)."""
+    A = _f64(A)
+    m, n = A.shape
+    As = np.zeros((s, n), order="F")
+    rc = lib().oracle_srft_sketch(m, n, _ptr(A), m, s, seed, pid, PREC[prec], _ptr(As), s)
+    if rc:
+        raise ValueError(f"oracle_srft_sketch failed: {rc}")
+    return As
+
+
+def srft_entries(A, s: int, seed: int, rows, cols, prec: str = "fp64", pid: int = 0) -> np.ndarray:
+    """Entries (rows[t], cols[t]) of the SRFT sketch, one by one."""
+    A = _f64(A)
+    m = A.shape[0]
+    rows = np.ascontiguousarray(rows, dtype=np.int64)
+    cols = np.ascontiguousarray(cols, dtype=np.int64)
+    out = np.zeros(rows.size)
+    rc = lib().oracle_srft_entries(m, _ptr(A), m, s, seed, pid, PREC[prec], rows.size, _ptr(rows), _ptr(cols),
+                                   _ptr(out))
+    if rc:
+        raise ValueError(f"oracle_srft_entries failed: {rc}")
+    return out

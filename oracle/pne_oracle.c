@@ -620,7 +620,8 @@ double oracle_fp16_qr_scale(int64_t s, int64_t n, const double* As, int64_t ldas
  * preconditioned normal equations A_p^T A_p y = A_p^T b, R_s x = y; HPNE:
  * A_p^T A x = A_p^T b solved by LU with partial pivoting).
  *   1. precision: sketch_prec / qr_prec, AUTO = condition-estimate pick
- *   2. A_s = Omega A in the sketch precision (oracle_sketch emulation)
+ *   2. A_s = Omega A in the sketch precision (oracle_sketch emulation; with
+ *      sketch_kind 1 the SRFT sketch oracle_srft_sketch instead)
  *   3. thin QR of A_s: A_s rounded to the QR precision, FP64 Householder,
  *      R_s rounded to the QR precision, then promoted to FP64 (Algorithm 1,
  *      "Promote R_s ... to double precision")
@@ -635,10 +636,13 @@ double oracle_fp16_qr_scale(int64_t s, int64_t n, const double* As, int64_t ldas
  * Outputs x (n), optionally R_s (n x n, ldr = n), the chosen precision and
  * kappa0.  Returns the numerical status (0 or 1000+k/2000+k/3000+k).
  * ---------------------------------------------------------------------- */
+int oracle_srft_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                       uint32_t pid, int prec, double* As, int64_t ldas);
+
 int oracle_solve(int hpne, int64_t m, int64_t n, const double* A, int64_t lda, const double* b,
                  int64_t s, uint64_t seed, uint32_t pid, int sketch_prec, int qr_prec,
-                 int64_t block_rows, int refine_steps, double known_kappa, double* x, double* R_out,
-                 int32_t* prec_used, float* kappa0_out)
+                 int64_t block_rows, int refine_steps, double known_kappa, int sketch_kind, double* x,
+                 double* R_out, int32_t* prec_used, float* kappa0_out)
 {
     if (m < n || n < 1 || lda < m || s < n) return -1;
     float kappa0 = NAN;
@@ -665,7 +669,10 @@ int oracle_solve(int hpne, int64_t m, int64_t n, const double* A, int64_t lda, c
     int info = 0;
     if (!As || !R || !Ap || !C || !c || !y || !r || !d || !piv) { info = -2; goto done; }
 
-    info = oracle_sketch(m, n, A, lda, s, seed, pid, sketch_prec, block_rows, As, s, NULL);
+    /* (the SRFT has no FP16 variant: an FP16 sketch precision runs as FP32) */
+    info = sketch_kind == 1 ? oracle_srft_sketch(m, n, A, lda, s, seed, pid,
+                                                 sketch_prec == PREC_FP16 ? PREC_FP32 : sketch_prec, As, s)
+                            : oracle_sketch(m, n, A, lda, s, seed, pid, sketch_prec, block_rows, As, s, NULL);
     if (info) goto done;
     /* FP16 has a narrow exponent range: the sketch is scaled by a power of
      * two before the rounding and R_s unscaled after it (exact), so that the
@@ -945,4 +952,105 @@ done:
     if (choice_out) *choice_out = pick_precision(k0);
     free(As); free(W); free(v); free(x); free(y); free(z);
     return rc;
+}
+
+/* ------------------------------------------------------------------------
+ * Subsampled randomized trigonometric transform (Section 6.2, eq. e_sketch:
+ * Omega = S F D), in its real form: F is the discrete Hartley transform
+ * (H)_{kj} = cas(2 pi k j / m') = cos + sin of that angle, which equals
+ * Re(F) - Im(F) of the DFT matrix F_{kj} = exp(-2 pi i k j / m') and is
+ * orthogonal up to the factor sqrt(m') -- a real trigonometric transform of
+ * the kind Section 7.1 names ("subsampled trigonometric transform").
+ *   m' = the smallest 7-smooth integer >= m (A is padded with zero rows:
+ *        the sketch of the padded matrix is a sketch of A);
+ *   D  = diag(d_j), d_j = +-1 for j < m': bit (j mod 128) of the 128-bit
+ *        Philox4x32-10 output at key (seed), counter (j / 128, 0, pid, 3)
+ *        (word (j mod 128) / 32, bit j mod 32; bit 1 -> -1);
+ *   S  = rows k_0..k_{s-1} of I_{m'} sampled uniformly with replacement:
+ *        k_i = floor(w m' / 2^64), w = w0 + 2^32 w1 from Philox at key
+ *        (seed), counter (i, 0, pid, 2);
+ *   A_s = (1 / sqrt(s)) S H D A  (E[Omega^T Omega] = I: H / sqrt(m') is
+ *        orthogonal and each sampled row carries the factor sqrt(m' / s)).
+ * Operands: A rounded to the sketch precision via FP32 (FP32, BF16; FP64
+ * unrounded), products summed in FP64 with the angle reduced exactly
+ * ((j k) mod m' in integers).
+ * ---------------------------------------------------------------------- */
+int64_t oracle_next_smooth(int64_t m)
+{
+    for (int64_t x = (m < 1 ? 1 : m);; ++x) {
+        int64_t y = x;
+        static const int primes[4] = {2, 3, 5, 7};
+        for (int p = 0; p < 4; ++p)
+            while (y % primes[p] == 0) y /= primes[p];
+        if (y == 1) return x;
+    }
+}
+
+int oracle_srft_sign(uint64_t seed, uint32_t pid, int64_t j)
+{
+    uint32_t ctr[4] = {(uint32_t)(j / 128), 0u, pid, 3u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    int64_t b = j % 128;
+    return ((w[b / 32] >> (b % 32)) & 1u) ? -1 : 1;
+}
+
+int64_t oracle_srft_index(uint64_t seed, uint32_t pid, int64_t i, int64_t mp)
+{
+    uint32_t ctr[4] = {(uint32_t)i, 0u, pid, 2u};
+    uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
+    uint32_t w[4];
+    oracle_philox4x32_10(ctr, key, w);
+    uint64_t u = (uint64_t)w[0] | ((uint64_t)w[1] << 32);
+    return (int64_t)(((unsigned __int128)u * (unsigned __int128)(uint64_t)mp) >> 64);
+}
+
+int oracle_srft_sketch(int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                       uint32_t pid, int prec, double* As, int64_t ldas)
+{
+    if (m < 1 || n < 1 || s < 1 || lda < m || ldas < s) return -1;
+    if (prec != PREC_FP64 && prec != PREC_FP32 && prec != PREC_BF16) return -1;
+    int64_t mp = oracle_next_smooth(m);
+    double* da = (double*)malloc(sizeof(double) * (size_t)m);
+    if (!da) return -2;
+    const double pi = 3.14159265358979323846;
+    for (int64_t c = 0; c < n; ++c) {
+        for (int64_t j = 0; j < m; ++j)
+            da[j] = oracle_srft_sign(seed, pid, j) * to_operand(A[IDX(j, c, lda)], prec);
+        for (int64_t i = 0; i < s; ++i) {
+            int64_t k = oracle_srft_index(seed, pid, i, mp);
+            double acc = 0.0;
+            for (int64_t j = 0; j < m; ++j) {
+                int64_t t = (int64_t)(((unsigned __int128)(uint64_t)j * (uint64_t)k) % (uint64_t)mp);
+                double ang = 2.0 * pi * (double)t / (double)mp;
+                acc += (cos(ang) + sin(ang)) * da[j];
+            }
+            As[IDX(i, c, ldas)] = acc / sqrt((double)s);
+        }
+    }
+    free(da);
+    return 0;
+}
+
+/* Selected entries (rows[t], cols[t]) of the SRFT sketch, each computed as in
+ * oracle_srft_sketch (checks of very large sketches). */
+int oracle_srft_entries(int64_t m, const double* A, int64_t lda, int64_t s, uint64_t seed, uint32_t pid,
+                        int prec, int64_t count, const int64_t* rows, const int64_t* cols, double* out)
+{
+    if (m < 1 || s < 1 || lda < m) return -1;
+    if (prec != PREC_FP64 && prec != PREC_FP32 && prec != PREC_BF16) return -1;
+    int64_t mp = oracle_next_smooth(m);
+    const double pi = 3.14159265358979323846;
+    for (int64_t t = 0; t < count; ++t) {
+        int64_t k = oracle_srft_index(seed, pid, rows[t], mp);
+        double acc = 0.0;
+        for (int64_t j = 0; j < m; ++j) {
+            int64_t r = (int64_t)(((unsigned __int128)(uint64_t)j * (uint64_t)k) % (uint64_t)mp);
+            double ang = 2.0 * pi * (double)r / (double)mp;
+            acc += (cos(ang) + sin(ang)) * oracle_srft_sign(seed, pid, j) * to_operand(A[IDX(j, cols[t], lda)], prec);
+        }
+        out[t] = acc / sqrt((double)s);
+    }
+    return 0;
 }

@@ -680,3 +680,94 @@ def test_cond_est_qr_overflow_is_double(orc):
     A[:, :4] = np.random.default_rng(84).standard_normal((50, 4))   # rank 4
     k0, ch = orc.cond_est_qr(A, seed=1)
     assert ch == 1 and (not math.isfinite(k0) or k0 > 8)
+
+
+# ---------------------------------------------------------------- SRFT sketch (Section 6.2, eq. e_sketch)
+
+def test_next_smooth_is_minimal_7_smooth(orc):
+    def smooth(x):
+        for p in (2, 3, 5, 7):
+            while x % p == 0:
+                x //= p
+        return x == 1
+    for m in list(range(1, 600)) + [1999, 4097, 100003, 999983]:
+        mp = orc.next_smooth(m)
+        assert mp >= m and smooth(mp)
+        assert all(not smooth(x) for x in range(m, mp))
+
+
+@pytest.mark.parametrize("m,prec", [(60, "fp64"), (97, "fp64"), (250, "fp32"), (131, "bf16")])
+def test_srft_matches_dense_hartley_product(orc, m, prec):
+    """The oracle's SRFT equals (1/sqrt(s)) S H D A with H = Re(F) - Im(F)
+    formed from numpy's FFT of the identity (F_kj = exp(-2 pi i k j / m')),
+    the zero-padded rows dropped, and A rounded by torch's conversions."""
+    rng = np.random.default_rng(m)
+    A = rng.standard_normal((m, 7)) * 10.0 ** rng.uniform(-3, 3, size=7)
+    s = 40
+    mp = orc.next_smooth(m)
+    D = orc.srft_signs(11, mp, pid=2)
+    k = orc.srft_indices(11, s, mp, pid=2)
+    F = np.fft.fft(np.eye(mp))
+    H = F.real - F.imag
+    Om = H[k][:, :m] * D[:m] / math.sqrt(s)
+    Aq = A
+    if prec == "fp32":
+        Aq = A.astype(np.float32).astype(np.float64)
+    elif prec == "bf16":
+        Aq = torch.tensor(A, dtype=torch.float32).to(torch.bfloat16).double().numpy()
+    ref = Om @ Aq
+    got = orc.srft_sketch(A, s, 11, prec=prec, pid=2)
+    assert np.allclose(got, ref, rtol=1e-12, atol=1e-12 * np.abs(ref).max())
+    # H / sqrt(m') is orthogonal (the Hartley transform is an involution up to m')
+    assert np.allclose(H @ H, mp * np.eye(mp), atol=1e-9 * mp)
+
+
+def test_srft_sampling_and_signs(orc):
+    mp = 997 * 1 + 3          # 1000 bins
+    mp = orc.next_smooth(mp)
+    k = orc.srft_indices(5, 40000, mp)
+    assert k.min() >= 0 and k.max() < mp
+    counts = np.bincount(k, minlength=mp)
+    chi2 = ((counts - 40000 / mp) ** 2 / (40000 / mp)).sum()
+    assert sst.chi2.sf(chi2, mp - 1) > 1e-3
+    d = orc.srft_signs(5, 20000)
+    assert set(np.unique(d)) == {-1.0, 1.0} and abs(d.mean()) < 4 / math.sqrt(20000)
+    assert not np.array_equal(orc.srft_signs(5, 256, pid=1), orc.srft_signs(5, 256, pid=0))
+    assert not np.array_equal(orc.srft_indices(6, 50, mp), orc.srft_indices(5, 50, mp))
+
+
+def test_srft_subspace_embedding(orc):
+    """Section 6.2: with d = 3n sampled rows the preconditioned matrix tends
+    to have kappa(A_p) <~ 10; kappa(A_p) = kappa(Omega U) for the orthonormal
+    basis U of range(A)."""
+    rng = np.random.default_rng(33)
+    for m, n in [(2000, 50), (3000, 100)]:
+        U = np.linalg.qr(rng.standard_normal((m, n)))[0]
+        Y = orc.srft_sketch(U, 3 * n, 9)
+        sv = np.linalg.svd(Y, compute_uv=False)
+        assert sv[0] / sv[-1] < 10.0, sv[0] / sv[-1]
+        # a coherent basis (columns of the identity) is spread by H D as well
+        E = np.eye(m)[:, :n]
+        sv = np.linalg.svd(orc.srft_sketch(E, 3 * n, 9), compute_uv=False)
+        assert sv[0] / sv[-1] < 10.0
+
+
+@pytest.mark.parametrize("prec,refine", [("fp64", 0), ("fp32", 1), ("bf16", 1)])
+def test_pne_hpne_with_srft_sketch(orc, prec, refine):
+    p = make_problem(3000, 100, 1e6, 1e-6, seed=44)
+    A, b, xs = p.numpy_A(), p.numpy_b(), p.numpy_x_star()
+    err_qr = relerr(orc.qr_ls(A, b), xs)
+    qr_prec = "fp64" if prec == "fp64" else "fp32"
+    for hpne in (False, True):
+        r = orc.solve(A, b, hpne=hpne, s=300, seed=3, sketch_prec=prec, qr_prec=qr_prec, refine_steps=refine,
+                      sketch_kind="srft")
+        assert r["info"] == 0
+        assert relerr(r["x"], xs) <= 10 * err_qr
+
+
+def test_srft_entries_match_full_sketch(orc):
+    A = np.random.default_rng(45).standard_normal((500, 6))
+    for prec in ("fp64", "fp32", "bf16"):
+        As = orc.srft_sketch(A, 30, 4, prec=prec, pid=1)
+        r, c = np.array([0, 5, 29, 17]), np.array([0, 3, 5, 1])
+        assert np.array_equal(orc.srft_entries(A, 30, 4, r, c, prec=prec, pid=1), As[r, c])
