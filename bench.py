@@ -94,6 +94,24 @@ def time_solver(pne, prob, opts, steps, warmup, hpne=False, profile=False):
     return (t1 - t0) / steps, err, phases
 
 
+def time_qr_solver(pne, prob, steps, warmup):
+    """The FP64 Householder-QR least-squares solver (qr_ls_solve) on the
+    same problem: seconds per solve and relative error."""
+    import torch
+    x = torch.empty(prob.n, dtype=torch.float64, device="cuda")
+    for _ in range(warmup):
+        pne.qr_ls_solve(prob.A, prob.b, x=x)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        _, info = pne.qr_ls_solve(prob.A, prob.b, x=x)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    assert int(info.item()) == 0, f"qr solver info {int(info.item())}"
+    err = float(torch.linalg.norm(x - prob.x_star) / torch.linalg.norm(prob.x_star))
+    return (t1 - t0) / steps, err
+
+
 def mean_phases(phases):
     keys = phases[0].keys()
     out = {}
@@ -171,6 +189,22 @@ def time_batched(pne, steps, warmup):
         out[f"refine{refine}"] = {"solves_per_s": len(probs) / dt, "ms": dt * 1e3,
                                   "members_within_bound": int(ok), "info_nonzero": int((info != 0).sum()),
                                   "phases_ms": phases}
+    # the same batch as a plan (tables uploaded once) replayed as a hipGraph
+    o = pne.make_opts(seed=0, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan = pne.BatchPlan(A, b, x, descs, opts=o, stream=st)
+        plan.execute_graph(st)
+        st.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            info = plan.execute_graph(st)
+        st.synchronize()
+        t1 = time.perf_counter()
+        plan.close()
+    dt = (t1 - t0) / steps
+    out["refine1_plan_graph"] = {"solves_per_s": len(probs) / dt, "ms": dt * 1e3,
+                                 "info_nonzero": int((info != 0).sum())}
     return out
 
 
@@ -343,6 +377,14 @@ def main():
         th, eh, phh = time_solver(pne, prob, mixed, args.steps, args.warmup, hpne=True, profile=True)
         print("[bench] timing FP64 HPNE", file=sys.stderr, flush=True)
         th64, eh64, phh64 = time_solver(pne, prob, fp64, args.steps, args.warmup, hpne=True, profile=True)
+        # the paper's GPU setting (Section 7.4): SRFT sketch, FP32 preconditioner
+        srft32 = pne.make_opts(s=S, seed=2, sketch_prec="fp32", qr_prec="fp32", refine_steps=0, sketch_kind="srft")
+        srftbf = pne.make_opts(s=S, seed=2, sketch_prec="bf16", qr_prec="fp32", refine_steps=1, sketch_kind="srft")
+        print("[bench] timing SRFT PNE", file=sys.stderr, flush=True)
+        ts32, es32, phs32 = time_solver(pne, prob, srft32, args.steps, args.warmup, profile=True)
+        tsbf, esbf, _ = time_solver(pne, prob, srftbf, args.steps, args.warmup)
+        print("[bench] timing the FP64 QR solver", file=sys.stderr, flush=True)
+        tq, eq = time_qr_solver(pne, prob, args.steps, args.warmup)
         out_extra = {
             "fp64_pne": {"solves_per_s": 1.0 / t64, "ms": t64 * 1e3, "rel_err": e64,
                          "phases_ms": {k: round(v, 4) for k, v in mean_phases(ph64).items()}},
@@ -351,6 +393,12 @@ def main():
                            "phases_ms": {k: round(v, 4) for k, v in mean_phases(phh).items()}},
             "fp64_hpne": {"solves_per_s": 1.0 / th64, "ms": th64 * 1e3, "rel_err": eh64,
                           "phases_ms": {k: round(v, 4) for k, v in mean_phases(phh64).items()}},
+            "srft_fp32_precond_pne": {"solves_per_s": 1.0 / ts32, "ms": ts32 * 1e3, "rel_err": es32,
+                                      "phases_ms": {k: round(v, 4) for k, v in mean_phases(phs32).items()}},
+            "srft_bf16_pne_refine1": {"solves_per_s": 1.0 / tsbf, "ms": tsbf * 1e3, "rel_err": esbf},
+            "qr_solver": {"solves_per_s": 1.0 / tq, "ms": tq * 1e3, "rel_err": eq,
+                          "kind": "FP64 Householder QR of [A b] (TSQR tree), Q never formed"},
+            "speedup_vs_qr_solver": tq / t_mix,
             "speedup_vs_fp64": t64 / t_mix,
             "hpne_speedup_vs_fp64": th64 / th,
             "equal_error": bool(e_mix <= 10 * max(e64, bound * 1e-3) and e_mix <= 10 * bound),

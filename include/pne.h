@@ -77,6 +77,12 @@ typedef struct {
     double known_kappa;     /* > 0: skip the estimate, pick from log10(known_kappa)      */
     int32_t refine_steps;   /* FP64 residual corrections after the solve (default 1)     */
     int32_t block_rows;     /* rows per scale block for FP16/FP8 sketches (128; mult. of 64) */
+    int32_t cond_method;    /* AUTO estimate: 0 = FP32 Gram (Section 6.1, default);
+                               1 = FP32 QR of the FP32 sketch (see cond_est_qr)              */
+    int32_t sketch_kind;    /* 0 = Gaussian (default); 1 = SRFT, the subsampled randomized
+                               trigonometric transform of Section 6.2 (see pne_sketch_srft);
+                               with SRFT an FP16 sketch precision runs as FP32, FP8 is not
+                               supported                                                    */
 } pne_opts;
 
 typedef struct {
@@ -88,7 +94,7 @@ typedef struct {
 
 /* Fills *opts with the defaults: s = 0 (3n), seed = 0, problem_id = 0,
  * sketch_prec = qr_prec = AUTO, known_kappa = 0, refine_steps = 1,
- * block_rows = 128. */
+ * block_rows = 128, cond_method = 0, sketch_kind = 0. */
 void pne_default_opts(pne_opts* opts);
 
 /* Bytes of workspace pne_solve (hpne = 0) or hpne_solve (hpne = 1) needs for
@@ -141,6 +147,49 @@ size_t cond_est_workspace_size(int64_t m, int64_t n);
 pne_status cond_est(int64_t m, int64_t n, const double* dA, int64_t lda, float* dkappa0,
                     int32_t* dchoice, void* dwork, size_t work_bytes, pne_stream_t stream);
 
+/* cond_est_qr: a condition estimate that does not square kappa(A) (a
+ * library variant of the single-precision estimate of Section 6.1, for the
+ * single-precision band of Algorithm 1 that the FP32 Gram estimate cannot
+ * reach beyond kappa ~ 4e3).  A_s = Omega A with the FP32 sketch (s rows, 0
+ * selects 3n; Omega as in pne_solve with problem_id 0), FP32 Householder QR
+ * A_s = Q R, Hager's estimate of ||R^{-1}||_1 (at most five iterations),
+ * kappa0 = log10(||R||_1 est) to *dkappa0 (+inf when a diagonal entry of R
+ * is zero or not finite); *dchoice by the thresholds of cond_est.  kappa(A_s)
+ * is within the condition number of the sketched orthonormal basis (< 3.73
+ * for s = 3n) of kappa(A).  pne_opts.cond_method = 1 makes AUTO use this
+ * estimate; when it picks FP32 for both steps, its R is the preconditioner
+ * (the FP32 sketch and QR are not repeated).
+ * Workspace: cond_est_qr_workspace_size. */
+size_t cond_est_qr_workspace_size(int64_t m, int64_t n, int64_t s);
+pne_status cond_est_qr(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
+                       float* dkappa0, int32_t* dchoice, void* dwork, size_t work_bytes, pne_stream_t stream);
+
+/* nne_solve: the not-normal equations B^T A x = B^T b (Section 5.2, eq.
+ * e_nne) for a caller-supplied B (m x n, ldb >= m, rank n, with the column
+ * space of A; then x is the least-squares solution).  C = B^T A and
+ * c = B^T b (FP64), LU with partial pivoting (first index of the largest
+ * magnitude), L U x = P c; then refine_steps FP64 corrections r = b - A x,
+ * d from B^T A d = B^T r (same LU), x += d.  The HPNE is the case B = A_p.
+ * dA, dB: m x n; db: m; dx: n (output); dinfo: one device int32 (3000+k on a
+ * zero or non-finite pivot; x is then NaN).  Workspace: nne_workspace_size. */
+size_t nne_workspace_size(int64_t m, int64_t n);
+pne_status nne_solve(int64_t m, int64_t n, const double* dA, int64_t lda, const double* dB, int64_t ldb,
+                     const double* db, double* dx, int32_t refine_steps, void* dwork, size_t work_bytes,
+                     int32_t* dinfo, pne_stream_t stream);
+
+/* qr_ls_solve: least squares by FP64 Householder QR on the GPU -- the
+ * direct QR solver the paper measures PNE/HPNE against (Section 7.4), with
+ * Q never formed: the QR of the augmented matrix [A b] = Q [R_A c; 0 rho]
+ * gives x = R_A^{-1} c.  The tall QR is a tree of blocked Householder QRs
+ * (TSQR): row blocks of at most 6144 rows are factored together, then groups
+ * of their stacked R factors, until one R remains.  n <= 3070.  dA: m x n
+ * (lda >= m); db: m; dx: n (output); dinfo: one device int32 (1000+k for a
+ * zero or non-finite R_A(k,k); x is then NaN).  Uploads one launch table per
+ * tree level (one wait each).  Workspace: qr_ls_workspace_size. */
+size_t qr_ls_workspace_size(int64_t m, int64_t n);
+pne_status qr_ls_solve(int64_t m, int64_t n, const double* dA, int64_t lda, const double* db, double* dx,
+                       void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream);
+
 /* pne_sketch: the sketch step alone, A_s = Omega A (s x n, FP64 output,
  * ldas >= s) in precision `prec` (FP64, FP32, FP16, BF16, FP8E4M3), with the
  * operand rounding the solvers use.  Omega as in pne_solve.
@@ -149,6 +198,21 @@ size_t pne_sketch_workspace_size(int64_t m, int64_t n, int64_t s, int32_t prec);
 pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
                       uint32_t problem_id, int32_t prec, int32_t block_rows, double* dAs,
                       int64_t ldas, void* dwork, size_t work_bytes, pne_stream_t stream);
+
+/* pne_sketch_srft: the SRFT sketch alone (Section 6.2, eq. e_sketch,
+ * Omega = S F D, with the real Hartley transform H = Re(F) - Im(F) as F):
+ * A_s = (1/sqrt(s)) S H D A, H of length m' = the smallest 7-smooth integer
+ * >= m (A padded with zero rows), D = diag(+-1) (bit j mod 128 of Philox at
+ * counter (j/128, 0, problem_id, 3)), S = s rows of I_m' sampled uniformly
+ * with replacement (k_i = floor(w m' / 2^64), w = the first two Philox words
+ * at counter (i, 0, problem_id, 2)); key = seed.  Computed by a mixed-radix
+ * FFT (radices 2..32) of paired columns, the last pass evaluated only at the
+ * sampled rows; arithmetic FP64 (prec FP64) or FP32 (FP32, or BF16 operands).
+ * dAs: s x n FP64 (ldas >= s).  Workspace: pne_sketch_srft_workspace_size. */
+size_t pne_sketch_srft_workspace_size(int64_t m, int64_t n, int32_t prec);
+pne_status pne_sketch_srft(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
+                           uint32_t problem_id, int32_t prec, double* dAs, int64_t ldas, void* dwork,
+                           size_t work_bytes, pne_stream_t stream);
 
 /* Batched PNE/HPNE (many independent problems in one call).
  * Problem i is A_i (m_i x n_i, lda_i) at dA_base + a_offset_i doubles, b_i at
@@ -168,6 +232,60 @@ pne_status pne_solve_batched(int64_t batch, const pne_problem_desc* hdesc, const
                              const double* db_base, double* dx_base, const pne_opts* opts,
                              int hpne, void* dwork, size_t work_bytes, int32_t* dinfo,
                              pne_stream_t stream);
+
+/* Batch plans: a batched solve prepared once and executed many times.
+ * pne_batch_plan_create checks the arguments, resolves AUTO precisions (the
+ * condition estimate runs once on the data present; the picks stay fixed
+ * for the plan's life), records the grouped launch sequence under the tuned
+ * parameters of the workload (see pne_autotune_batched) and uploads its
+ * launch tables into dwork (one wait for the upload).  The workspace, A, b,
+ * x and dinfo of the create call are bound to the plan: they must stay
+ * allocated, and the plan may only be executed on data of the same shapes
+ * at the same addresses.  Workspace size: pne_batched_workspace_size.
+ * pne_batch_plan_execute enqueues the solve on `stream` -- kernel launches
+ * only (the info words are cleared by a kernel), no copies, no host waits,
+ * so it can be captured into a hipGraph by the caller.
+ * pne_batch_plan_execute_graph captures the same sequence into a hipGraph
+ * on its first call (stream must not be NULL, the legacy default stream
+ * cannot be captured) and launches the instantiated graph on this and every
+ * later call.  Executions of one plan must be ordered on one stream.  Results
+ * are bitwise identical between executions, graph or not. */
+typedef struct pne_batch_plan_s* pne_batch_plan;
+pne_status pne_batch_plan_create(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
+                                 const double* db_base, double* dx_base, const pne_opts* opts, int hpne,
+                                 void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream,
+                                 pne_batch_plan* plan);
+pne_status pne_batch_plan_execute(pne_batch_plan plan, pne_stream_t stream);
+pne_status pne_batch_plan_execute_graph(pne_batch_plan plan, pne_stream_t stream);
+void pne_batch_plan_destroy(pne_batch_plan plan);
+
+/* Autotuner of the batched path.  Times candidate launch parameters on the
+ * caller's batch (a plan per candidate; one warm-up and the median of three
+ * executions, HIP events on `stream`): the row chunk of the split-K products
+ * of a batch (4096, 8192, 16384), the output tile of the short-K products
+ * (64 or 128) and the largest order of the Gram products that use 64 x 64
+ * tiles (512 or 1024).  The fastest is written to *result and, when the
+ * environment variable PNE_TUNE_CACHE names a file, stored there (JSON)
+ * under a key of (solver, sketch and QR precision options, power-of-two
+ * buckets of the member count, mean n and mean m); pne_batched_workspace_size,
+ * pne_solve_batched and pne_batch_plan_create read the entry back for
+ * workloads with the same key.  x and dinfo hold the results of the last
+ * candidate's last execution.  Workspace: at least
+ * pne_autotune_batched_workspace_size (candidates that need more than
+ * work_bytes are skipped). */
+typedef struct {
+    int64_t batch_kchunk;
+    int32_t shortk_tile;
+    int32_t lower_small_n;
+    double ms;        /* median time of one execution with these parameters */
+    int32_t stored;   /* 1 if written to the cache file */
+} pne_tune_result;
+size_t pne_autotune_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* opts,
+                                           int hpne);
+pne_status pne_autotune_batched(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
+                                const double* db_base, double* dx_base, const pne_opts* opts, int hpne,
+                                void* dwork, size_t work_bytes, int32_t* dinfo, pne_stream_t stream,
+                                pne_tune_result* result);
 
 /* pne_gram: the normal-equation matrices of the solvers for a given
  * preconditioner (diagnostics and kernel-level checks).  With R (n x n,

@@ -28,7 +28,11 @@ EXPORTS = ["pne_default_opts", "pne_workspace_size", "pne_solve", "hpne_solve",
            "pne_sketch_workspace_size", "pne_sketch", "pne_batched_workspace_size",
            "pne_solve_batched", "pne_gram_workspace_size", "pne_gram", "pne_status_string",
            "pne_profile_enable", "pne_profile_read", "pne_profile_phase_name",
-           "pne_noalloc_max_bytes", "pne_solve_noalloc"]
+           "pne_noalloc_max_bytes", "pne_solve_noalloc", "cond_est_qr_workspace_size", "cond_est_qr",
+           "nne_workspace_size", "nne_solve", "pne_batch_plan_create", "pne_batch_plan_execute",
+           "pne_batch_plan_execute_graph", "pne_batch_plan_destroy", "pne_autotune_batched_workspace_size",
+           "pne_autotune_batched", "pne_sketch_srft_workspace_size", "pne_sketch_srft", "qr_ls_workspace_size",
+           "qr_ls_solve"]
 
 
 class PneError(RuntimeError):
@@ -41,12 +45,18 @@ class Opts(ctypes.Structure):
     _fields_ = [("s", ctypes.c_int64), ("seed", ctypes.c_uint64), ("problem_id", ctypes.c_uint32),
                 ("sketch_prec", ctypes.c_int32), ("qr_prec", ctypes.c_int32),
                 ("known_kappa", ctypes.c_double), ("refine_steps", ctypes.c_int32),
-                ("block_rows", ctypes.c_int32)]
+                ("block_rows", ctypes.c_int32), ("cond_method", ctypes.c_int32),
+                ("sketch_kind", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
     _fields_ = [("sketch_prec_used", ctypes.c_int32), ("qr_prec_used", ctypes.c_int32),
                 ("kappa0", ctypes.c_float), ("refine_steps_run", ctypes.c_int32)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("batch_kchunk", ctypes.c_int64), ("shortk_tile", ctypes.c_int32),
+                ("lower_small_n", ctypes.c_int32), ("ms", ctypes.c_double), ("stored", ctypes.c_int32)]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -89,6 +99,23 @@ def lib():
             "pne_profile_read": (ctypes.c_int, [P, ctypes.c_int]),
             "pne_profile_phase_name": (ctypes.c_char_p, [ctypes.c_int]),
             "pne_noalloc_max_bytes": (sz, []),
+            "cond_est_qr_workspace_size": (sz, [i64, i64, i64]),
+            "cond_est_qr": (ctypes.c_int, [i64, i64, P, i64, i64, ctypes.c_uint64, P, P, P, sz, P]),
+            "nne_workspace_size": (sz, [i64, i64]),
+            "qr_ls_workspace_size": (sz, [i64, i64]),
+            "qr_ls_solve": (ctypes.c_int, [i64, i64, P, i64, P, P, P, sz, P, P]),
+            "pne_sketch_srft_workspace_size": (sz, [i64, i64, ctypes.c_int32]),
+            "pne_sketch_srft": (ctypes.c_int, [i64, i64, P, i64, i64, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_int32,
+                                               P, i64, P, sz, P]),
+            "pne_batch_plan_create": (ctypes.c_int, [i64, P, P, P, P, OP, ctypes.c_int, P, sz, P, P,
+                                                     ctypes.POINTER(ctypes.c_void_p)]),
+            "pne_batch_plan_execute": (ctypes.c_int, [P, P]),
+            "pne_batch_plan_execute_graph": (ctypes.c_int, [P, P]),
+            "pne_batch_plan_destroy": (None, [P]),
+            "pne_autotune_batched_workspace_size": (sz, [i64, P, OP, ctypes.c_int]),
+            "pne_autotune_batched": (ctypes.c_int, [i64, P, P, P, P, OP, ctypes.c_int, P, sz, P, P,
+                                                    ctypes.POINTER(TuneResult)]),
+            "nne_solve": (ctypes.c_int, [i64, i64, P, i64, P, i64, P, P, ctypes.c_int32, P, sz, P, P]),
             "pne_solve_noalloc": (ctypes.c_int, [i64, i64, P, i64, P, P, OP, ctypes.c_int, P, P, P]),
         }
         for name, (res, args) in sigs.items():
@@ -100,7 +127,8 @@ def lib():
 
 
 def make_opts(s: int = 0, seed: int = 0, problem_id: int = 0, sketch_prec="auto", qr_prec=None,
-              known_kappa: float = 0.0, refine_steps: int = 1, block_rows: int = 128) -> Opts:
+              known_kappa: float = 0.0, refine_steps: int = 1, block_rows: int = 128,
+              cond_method: int = 0, sketch_kind="gaussian") -> Opts:
     o = Opts()
     lib().pne_default_opts(ctypes.byref(o))
     o.s = int(s)
@@ -112,6 +140,8 @@ def make_opts(s: int = 0, seed: int = 0, problem_id: int = 0, sketch_prec="auto"
     o.known_kappa = float(known_kappa)
     o.refine_steps = int(refine_steps)
     o.block_rows = int(block_rows)
+    o.cond_method = int(cond_method)
+    o.sketch_kind = {"gaussian": 0, "srft": 1}[sketch_kind] if isinstance(sketch_kind, str) else int(sketch_kind)
     return o
 
 
@@ -233,6 +263,43 @@ def cond_est(A, stream=None, workspace=None):
     return k0, ch
 
 
+def cond_est_qr(A, s: int = 0, seed: int = 0, stream=None, workspace=None):
+    """(kappa0, precision code) device tensors from the FP32 QR of the FP32
+    sketch (include/pne.h cond_est_qr)."""
+    m, n, lda = _colmajor(A)
+    k0 = torch.empty(1, dtype=torch.float32, device=A.device)
+    ch = torch.empty(1, dtype=torch.int32, device=A.device)
+    need = lib().cond_est_qr_workspace_size(m, n, s)
+    if need == 0:
+        raise PneError("cond_est_qr_workspace_size", -1)
+    ws = (workspace or _ws).get(need, A.device)
+    rc = lib().cond_est_qr(m, n, A.data_ptr(), lda, s, seed, k0.data_ptr(), ch.data_ptr(), ws.data_ptr(),
+                           ws.numel(), _stream_ptr(stream))
+    _check("cond_est_qr", rc)
+    return k0, ch
+
+
+def nne_solve(A, B, b, x=None, refine_steps: int = 0, stream=None, workspace=None):
+    """Not-normal equations B^T A x = B^T b (include/pne.h nne_solve).
+    A and B column-major (m, n) float64 CUDA tensors.  Returns (x, info)."""
+    m, n, lda = _colmajor(A)
+    mb, nb, ldb = _colmajor(B)
+    if (mb, nb) != (m, n):
+        raise ValueError("B must have the shape of A")
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m:
+        raise ValueError("b must be a contiguous float64 vector of length m")
+    x = torch.empty(n, dtype=torch.float64, device=A.device) if x is None else x
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    need = lib().nne_workspace_size(m, n)
+    if need == 0:
+        raise PneError("nne_workspace_size", -1)
+    ws = (workspace or _ws).get(need, A.device)
+    rc = lib().nne_solve(m, n, A.data_ptr(), lda, B.data_ptr(), ldb, b.data_ptr(), x.data_ptr(), refine_steps,
+                         ws.data_ptr(), ws.numel(), info.data_ptr(), _stream_ptr(stream))
+    _check("nne_solve", rc)
+    return x, info
+
+
 def pne_sketch(A, s: int, seed: int = 0, problem_id: int = 0, prec="fp64", block_rows: int = 128,
                stream=None, workspace=None):
     """A_s = Omega A (s x n FP64 column-major view)."""
@@ -246,6 +313,39 @@ def pne_sketch(A, s: int, seed: int = 0, problem_id: int = 0, prec="fp64", block
     rc = lib().pne_sketch(m, n, A.data_ptr(), lda, s, seed, problem_id, p, block_rows, Ast.data_ptr(), s,
                           ws.data_ptr(), ws.numel(), _stream_ptr(stream))
     _check("pne_sketch", rc)
+    return Ast.t()
+
+
+def qr_ls_solve(A, b, x=None, stream=None, workspace=None):
+    """FP64 Householder-QR least-squares solve (include/pne.h qr_ls_solve).
+    Returns (x, info)."""
+    m, n, lda = _colmajor(A)
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != m:
+        raise ValueError("b must be a contiguous float64 vector of length m")
+    x = torch.empty(n, dtype=torch.float64, device=A.device) if x is None else x
+    info = torch.zeros(1, dtype=torch.int32, device=A.device)
+    need = lib().qr_ls_workspace_size(m, n)
+    if need == 0:
+        raise PneError("qr_ls_workspace_size", -1)
+    ws = (workspace or _ws).get(need, A.device)
+    rc = lib().qr_ls_solve(m, n, A.data_ptr(), lda, b.data_ptr(), x.data_ptr(), ws.data_ptr(), ws.numel(),
+                           info.data_ptr(), _stream_ptr(stream))
+    _check("qr_ls_solve", rc)
+    return x, info
+
+
+def pne_sketch_srft(A, s: int, seed: int = 0, problem_id: int = 0, prec="fp64", stream=None, workspace=None):
+    """SRFT sketch A_s = (1/sqrt(s)) S H D A (s x n FP64 column-major view)."""
+    m, n, lda = _colmajor(A)
+    p = PREC[prec] if isinstance(prec, str) else int(prec)
+    Ast = torch.empty(n, s, dtype=torch.float64, device=A.device)
+    need = lib().pne_sketch_srft_workspace_size(m, n, p)
+    if need == 0:
+        raise PneError("pne_sketch_srft_workspace_size", -1)
+    ws = (workspace or _ws).get(need, A.device)
+    rc = lib().pne_sketch_srft(m, n, A.data_ptr(), lda, s, seed, problem_id, p, Ast.data_ptr(), s, ws.data_ptr(),
+                               ws.numel(), _stream_ptr(stream))
+    _check("pne_sketch_srft", rc)
     return Ast.t()
 
 
@@ -293,3 +393,79 @@ def pne_gram(A, b, R, hpne: bool = False, factor: bool = False, stream=None, wor
                         ws.data_ptr(), ws.numel(), info.data_ptr(), _stream_ptr(stream))
     _check("pne_gram", rc)
     return Ct.t(), c, piv, info
+
+
+def _desc_array(descs):
+    arr = (ProblemDesc * len(descs))()
+    for i, d in enumerate(descs):
+        arr[i] = ProblemDesc(d["m"], d["n"], d["lda"], d["a_offset"], d["b_offset"], d["x_offset"],
+                             d.get("problem_id", i))
+    return arr
+
+
+class BatchPlan:
+    """A batched solve prepared once (include/pne.h pne_batch_plan_create) and
+    executed many times.  Owns its workspace tensor; A, b, x must stay alive
+    and in place while the plan is used."""
+
+    def __init__(self, A_base, b_base, x_base, descs, opts: Opts | None = None, hpne: bool = False, stream=None):
+        self.opts = opts or make_opts()
+        self.arr = _desc_array(descs)
+        batch = len(descs)
+        self.info = torch.zeros(batch, dtype=torch.int32, device=A_base.device)
+        need = lib().pne_batched_workspace_size(batch, ctypes.cast(self.arr, ctypes.c_void_p),
+                                                ctypes.byref(self.opts), int(hpne))
+        if need == 0:
+            raise PneError("pne_batched_workspace_size", -1)
+        self.ws = torch.empty(need, dtype=torch.uint8, device=A_base.device)
+        self._keep = (A_base, b_base, x_base)
+        h = ctypes.c_void_p()
+        rc = lib().pne_batch_plan_create(batch, ctypes.cast(self.arr, ctypes.c_void_p), A_base.data_ptr(),
+                                         b_base.data_ptr(), x_base.data_ptr(), ctypes.byref(self.opts), int(hpne),
+                                         self.ws.data_ptr(), self.ws.numel(), self.info.data_ptr(),
+                                         _stream_ptr(stream), ctypes.byref(h))
+        _check("pne_batch_plan_create", rc)
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check("pne_batch_plan_execute", lib().pne_batch_plan_execute(self.handle, _stream_ptr(stream)))
+        return self.info
+
+    def execute_graph(self, stream):
+        """Capture on the first call, then launch the instantiated hipGraph
+        (stream: a non-default torch.cuda.Stream)."""
+        _check("pne_batch_plan_execute_graph", lib().pne_batch_plan_execute_graph(self.handle, _stream_ptr(stream)))
+        return self.info
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().pne_batch_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def autotune_batched(A_base, b_base, x_base, descs, opts: Opts | None = None, hpne: bool = False, stream=None):
+    """Autotuner of the batched path (include/pne.h pne_autotune_batched).
+    Returns a dict with the chosen parameters, their time and whether they
+    were stored in $PNE_TUNE_CACHE."""
+    opts = opts or make_opts()
+    arr = _desc_array(descs)
+    batch = len(descs)
+    need = lib().pne_autotune_batched_workspace_size(batch, ctypes.cast(arr, ctypes.c_void_p), ctypes.byref(opts),
+                                                     int(hpne))
+    if need == 0:
+        raise PneError("pne_autotune_batched_workspace_size", -1)
+    ws = torch.empty(need, dtype=torch.uint8, device=A_base.device)
+    info = torch.zeros(batch, dtype=torch.int32, device=A_base.device)
+    res = TuneResult()
+    rc = lib().pne_autotune_batched(batch, ctypes.cast(arr, ctypes.c_void_p), A_base.data_ptr(), b_base.data_ptr(),
+                                    x_base.data_ptr(), ctypes.byref(opts), int(hpne), ws.data_ptr(), ws.numel(),
+                                    info.data_ptr(), _stream_ptr(stream), ctypes.byref(res))
+    _check("pne_autotune_batched", rc)
+    return {"batch_kchunk": res.batch_kchunk, "shortk_tile": res.shortk_tile, "lower_small_n": res.lower_small_n,
+            "ms": res.ms, "stored": bool(res.stored)}

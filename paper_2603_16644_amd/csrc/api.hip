@@ -9,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "profile.h"
+#include "tune.h"
 
 using namespace pne;
 
@@ -21,7 +22,13 @@ struct Problem {
     int refine;
     int64_t br;
     int64_t kchunk_fixed;   // 0: one problem on the machine; > 0: batch planning
+    int cond_method;        // 0: FP32 Gram estimate (Section 6.1); 1: FP32 QR of the sketch
+    int sketch_kind;        // 0: Gaussian; 1: SRFT (Hartley transform)
 };
+
+// Precision the SRFT sketch runs in for a requested sketch precision: FP16
+// has no SRFT variant (its range would need scaling) and runs as FP32.
+inline int srft_prec(int sk) { return sk == PNE_PREC_FP16 ? PNE_PREC_FP32 : sk; }
 
 bool valid_prec(int p, bool allow_auto, bool allow_fp8)
 {
@@ -66,7 +73,8 @@ struct Buffers {
 
 size_t scratch_bytes(const Problem& p, int sk, int qr)
 {
-    size_t b = sketch_workspace_bytes(p.m, p.n, p.s, sk, p.br, p.kchunk_fixed);
+    size_t b = p.sketch_kind == 1 ? srft_workspace_bytes(p.m, p.n, srft_prec(sk))
+                                  : sketch_workspace_bytes(p.m, p.n, p.s, sk, p.br, p.kchunk_fixed);
     size_t q = qr_workspace_bytes(p.s, p.n, qr);
     if (q > b) b = q;
     int64_t splits, kc;
@@ -92,7 +100,8 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
             if (qr[j] == PNE_PREC_FP64) any64 = true;
         }
     if (with_condest) {
-        size_t ce = condest_workspace_bytes(p.m, p.n, p.kchunk_fixed);
+        size_t ce = p.cond_method == 1 ? condest_qr_workspace_bytes(p.m, p.n, p.s, p.kchunk_fixed)
+                                       : condest_workspace_bytes(p.m, p.n, p.kchunk_fixed);
         if (ce > scr) scr = ce;
     }
     Arena ar(base, cap);
@@ -133,6 +142,10 @@ pne_status check_common(int64_t m, int64_t n, const void* dA, int64_t lda, const
     if (!valid_prec(o->sketch_prec, true, true)) return PNE_EINVAL;
     if (!valid_prec(o->qr_prec, true, false)) return PNE_EINVAL;
     if (o->refine_steps < 0) return PNE_EINVAL;
+    if (o->cond_method != 0 && o->cond_method != 1) return PNE_EINVAL;
+    if (o->sketch_kind != 0 && o->sketch_kind != 1) return PNE_EINVAL;
+    if (o->sketch_kind == 1 && o->sketch_prec == PNE_PREC_FP8E4M3) return PNE_ENOTSUP;
+    if (o->cond_method == 1 && !qr_supported(s, PNE_PREC_FP32)) return PNE_ENOTSUP;
     const bool scaled = o->sketch_prec == PNE_PREC_FP8E4M3 || o->sketch_prec == PNE_PREC_FP16 ||
                         o->sketch_prec == PNE_PREC_AUTO;
     if (scaled && (o->block_rows < 64 || o->block_rows % 64 != 0)) return PNE_EINVAL;
@@ -155,12 +168,36 @@ Problem make_problem(int64_t m, int64_t n, int64_t lda, const pne_opts* o, int h
     p.refine = o->refine_steps;
     p.br = o->block_rows > 0 ? o->block_rows : 128;
     p.kchunk_fixed = kchunk_fixed;
+    p.cond_method = o->cond_method;
+    p.sketch_kind = o->sketch_kind;
     return p;
 }
 
 inline void mark(Exec& ex, int phase)
 {
     if (!ex.recording()) prof_mark(phase, ex.st);
+}
+
+// The condition estimate of one problem into b.k0 / b.choice: the FP32 Gram
+// estimate of Section 6.1, or (cond_method 1, no known kappa) the estimate
+// from the FP32 QR of the FP32 sketch, which leaves that sketch in b.W and
+// its R factor in b.R.
+int run_condest(Exec& ex, const Problem& p, const double* dA, const pne_opts* o, uint32_t pid, const Buffers& b,
+                size_t scratch_cap)
+{
+    if (p.cond_method == 1 && !(o->known_kappa > 0.0))
+        return condest_qr_run(ex, p.m, p.n, dA, p.lda, p.s, o->seed, pid, b.k0, b.choice, (float*)b.W, b.R,
+                              b.scratch, scratch_cap);
+    return condest_run(ex, p.m, p.n, dA, p.lda, o->known_kappa, b.k0, b.choice, b.scratch, scratch_cap);
+}
+
+// With the QR estimate and both precisions AUTO, an FP32 pick means the
+// estimate already computed the preconditioner (FP32 sketch, FP32 QR, same
+// seed and rows): R_s is in b.R and is reused as it stands.
+bool precond_from_condest(const Problem& p, const pne_opts* o, int sk, int qr)
+{
+    return p.cond_method == 1 && p.sketch_kind == 0 && !(o->known_kappa > 0.0) && p.sketch_prec == PNE_PREC_AUTO &&
+           p.qr_prec == PNE_PREC_AUTO && sk == PNE_PREC_FP32 && qr == PNE_PREC_FP32;
 }
 
 // Resolve AUTO through the condition estimate (one host synchronisation).
@@ -171,7 +208,7 @@ pne_status resolve_precision(Exec& ex, const Problem& p, const double* dA, const
     *qr = p.qr_prec;
     *k0 = NAN;
     if (*sk != PNE_PREC_AUTO && *qr != PNE_PREC_AUTO) return PNE_OK;
-    int rc = condest_run(ex, p.m, p.n, dA, p.lda, o->known_kappa, b.k0, b.choice, b.scratch, scratch_cap);
+    int rc = run_condest(ex, p, dA, o, o->problem_id, b, scratch_cap);
     if (rc) return (pne_status)rc;
     float hk0;
     int32_t hch;
@@ -192,9 +229,11 @@ pne_status run_precond(Exec& ex, const Problem& p, const double* dA, uint64_t se
 {
     const bool w64 = (qr == PNE_PREC_FP64);
     const size_t cap = scratch_cap_of(b);
-    int rc = sketch_run(ex, p.m, p.n, dA, p.lda, p.s, seed, pid, sk, p.br,
-                        w64 ? nullptr : (float*)b.W, p.s, w64 ? (double*)b.W : nullptr, p.s,
-                        b.scratch, cap);
+    int rc = p.sketch_kind == 1
+                 ? srft_run(ex, p.m, p.n, dA, p.lda, p.s, seed, pid, srft_prec(sk), w64 ? nullptr : (float*)b.W, p.s,
+                            w64 ? (double*)b.W : nullptr, p.s, b.scratch, cap)
+                 : sketch_run(ex, p.m, p.n, dA, p.lda, p.s, seed, pid, sk, p.br, w64 ? nullptr : (float*)b.W, p.s,
+                              w64 ? (double*)b.W : nullptr, p.s, b.scratch, cap);
     if (rc) return (pne_status)rc;
     rc = qr_r(ex, p.s, p.n, b.W, p.s, qr, b.R, p.n, dinfo, b.scratch, cap);
     mark(ex, PH_QR);
@@ -304,8 +343,10 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
     pne_status rc = resolve_precision(ex, p, dA, o, b, scratch_cap_of(b), &sk, &qr, &k0);
     if (rc) return rc;
     mark(ex, PH_CONDEST);
-    rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
-    if (rc) return rc;
+    if (!precond_from_condest(p, o, sk, qr)) {
+        rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
+        if (rc) return rc;
+    }
     rc = run_solve(ex, p, dA, db, dx, b, dinfo);
     if (rc) return rc;
     if (hipGetLastError() != hipSuccess) return PNE_EHIP;
@@ -320,9 +361,10 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
 
 // ---------------------------------------------------------------- batches
 // Row chunk of the split-K products in a batch: every member's long products
-// are cut into pieces of this many rows, so that work-groups carry similar
-// work across members of very different sizes.
-constexpr int64_t BATCH_KCHUNK = 8192;
+// are cut into pieces of TuneParams::batch_kchunk rows (8192 unless the
+// autotuner chose another length for the workload), so that work-groups
+// carry similar work across members of very different sizes.
+inline int64_t batch_kchunk() { return tune_params().batch_kchunk; }
 
 struct BatchLayout {
     float* k0;              // [batch] condition estimates
@@ -346,7 +388,7 @@ void batch_layout(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, 
     L->prob.resize(batch);
     const bool with_ce = batch_auto(o);
     for (int64_t i = 0; i < batch; ++i) {
-        L->prob[i] = make_problem(hd[i].m, hd[i].n, hd[i].lda, o, hpne, BATCH_KCHUNK);
+        L->prob[i] = make_problem(hd[i].m, hd[i].n, hd[i].lda, o, hpne, batch_kchunk());
         const size_t need = layout(L->prob[i], nullptr, 0, nullptr, with_ce, false);
         char* region = ar.take<char>(need);
         layout(L->prob[i], region, need, &L->buf[i], with_ce, false);
@@ -374,18 +416,23 @@ pne_status record_batch(Recorder& rec, int64_t batch, const pne_problem_desc* hd
                         const double* db_base, double* dx_base, const pne_opts* o, const BatchLayout& L,
                         const int32_t* sk, const int32_t* qr, int32_t* dinfo)
 {
+    // (members whose QR estimate already computed the FP32 preconditioner
+    // skip the sketch and QR)
     for (int64_t i = 0; i < batch; ++i) {
         Exec ex;
         ex.rec = &rec;
         ex.member = (int32_t)i;
-        ex.kchunk_fixed = BATCH_KCHUNK;
+        ex.kchunk_fixed = batch_kchunk();
         const Problem& p = L.prob[i];
         const double* A = dA_base ? dA_base + hd[i].a_offset : nullptr;
         const double* b = db_base ? db_base + hd[i].b_offset : nullptr;
         double* x = dx_base ? dx_base + hd[i].x_offset : nullptr;
-        pne_status rc = run_precond(ex, p, A, o->seed, (uint32_t)hd[i].problem_id, sk[i], qr[i], L.buf[i],
-                                     dinfo ? dinfo + i : nullptr);
-        if (rc) return rc;
+        pne_status rc = PNE_OK;
+        if (!precond_from_condest(p, o, sk[i], qr[i])) {
+            rc = run_precond(ex, p, A, o->seed, (uint32_t)hd[i].problem_id, sk[i], qr[i], L.buf[i],
+                             dinfo ? dinfo + i : nullptr);
+            if (rc) return rc;
+        }
         rc = run_solve(ex, p, A, b, x, L.buf[i], dinfo ? dinfo + i : nullptr);
         if (rc) return rc;
     }
@@ -399,11 +446,11 @@ pne_status record_condest(Recorder& rec, int64_t batch, const pne_problem_desc* 
         Exec ex;
         ex.rec = &rec;
         ex.member = (int32_t)i;
-        ex.kchunk_fixed = BATCH_KCHUNK;
+        ex.kchunk_fixed = batch_kchunk();
         const Problem& p = L.prob[i];
         const Buffers& b = L.buf[i];
-        int rc = condest_run(ex, p.m, p.n, dA_base ? dA_base + hd[i].a_offset : nullptr, p.lda, o->known_kappa,
-                             b.k0, b.choice, b.scratch, scratch_cap_of(b));
+        int rc = run_condest(ex, p, dA_base ? dA_base + hd[i].a_offset : nullptr, o, (uint32_t)hd[i].problem_id, b,
+                             scratch_cap_of(b));
         if (rc) return (pne_status)rc;
     }
     return PNE_OK;
@@ -430,7 +477,8 @@ size_t batched_size(int64_t batch, const pne_problem_desc* hd, const pne_opts* o
     // drivers non-null buffers with their real capacities
     BatchLayout L;
     batch_layout(batch, hd, o, hpne, (void*)(uintptr_t)0x100000, SIZE_MAX / 4, &L);
-    // table bound over every precision a member may use
+    // table bound over every precision a member may use, plus the condition
+    // estimate's tables (a plan keeps both resident)
     int sk[3], qr[3], nsk, nqr;
     candidates(o->sketch_prec, sk, &nsk);
     candidates(o->qr_prec, qr, &nqr);
@@ -449,10 +497,125 @@ size_t batched_size(int64_t batch, const pne_problem_desc* hd, const pne_opts* o
     if (batch_auto(o)) {
         Recorder rec;
         if (record_condest(rec, batch, hd, nullptr, o, L)) return 0;
-        size_t b = table_bound(rec);
-        if (b > tb) tb = b;
+        tb += table_bound(rec);
     }
     return L.fixed_bytes + tb;
+}
+
+// Tuned parameters of a batched workload (the cache entry of its key, else
+// the defaults).
+TuneParams batch_tune(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, int hpne)
+{
+    double sn = 0.0, sm = 0.0;
+    for (int64_t i = 0; i < batch; ++i) { sn += (double)hd[i].n; sm += (double)hd[i].m; }
+    TuneParams tp;
+    tune_lookup(tune_key_batched(hpne, o->sketch_prec, o->qr_prec, batch, sn / batch, sm / batch), &tp);
+    return tp;
+}
+
+}  // namespace
+
+// A batched solve prepared once and executed any number of times: the
+// precisions (AUTO resolved at creation), the tuned launch parameters, and
+// the grouped launch sequence with its tables resident in the workspace.
+struct pne_batch_plan_s {
+    int64_t batch = 0;
+    int32_t* dinfo = nullptr;
+    char* dtables = nullptr;
+    std::vector<pne::LaunchGroup> ce_groups;    // condition estimate (AUTO)
+    std::vector<pne::LaunchGroup> main_groups;  // the solves
+    pne::TuneParams tune;
+    bool rerun_ce = false;   // some member takes its preconditioner from the estimate
+    hipGraphExec_t gexec = nullptr;
+    ~pne_batch_plan_s()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+    }
+};
+
+namespace {
+
+// Builds a plan: records, groups and uploads the launch sequence (one wait
+// for the upload; with AUTO the estimate runs once and its picks are read
+// back).  Runs under the tuned parameters of the workload.
+pne_status plan_create(int64_t batch, const pne_problem_desc* hd, const double* dA_base, const double* db_base,
+                       double* dx_base, const pne_opts* o, int hpne, void* dwork, size_t work_bytes, int32_t* dinfo,
+                       hipStream_t st, const TuneParams& tp, pne_batch_plan_s** out)
+{
+    *out = nullptr;
+    pne_status chk = check_batch(batch, hd, o, hpne);
+    if (chk) return chk;
+    if (!dA_base || !db_base || !dx_base || !dinfo || !dwork) return PNE_EINVAL;
+    TuneScope scope(tp);
+    if (work_bytes < batched_size(batch, hd, o, hpne)) return PNE_EWORKSPACE;
+    BatchLayout L;
+    batch_layout(batch, hd, o, hpne, dwork, work_bytes, &L);
+    std::vector<int32_t> sk(batch, o->sketch_prec), qr(batch, o->qr_prec);
+    GroupSeq ce, mainseq;
+    size_t toff = 0;
+    if (batch_auto(o)) {
+        Recorder rec;
+        pne_status rc = record_condest(rec, batch, hd, dA_base, o, L);
+        if (rc) return rc;
+        rc = (pne_status)build_groups(rec, &ce);
+        if (rc) return rc;
+        if (ce.blob.size() > L.table_cap) return PNE_EWORKSPACE;
+        HIP_OK(hipMemcpyAsync(L.tables, ce.blob.data(), ce.blob.size(), hipMemcpyHostToDevice, st));
+        enqueue_groups(ce.groups, L.tables, st, false);
+        std::vector<int32_t> ch(batch);
+        HIP_OK(hipMemcpyAsync(ch.data(), L.choice, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_OK(hipStreamSynchronize(st));
+        if (hipGetLastError() != hipSuccess) return PNE_EHIP;
+        for (int64_t i = 0; i < batch; ++i) {
+            if (sk[i] == PNE_PREC_AUTO) sk[i] = ch[i];
+            if (qr[i] == PNE_PREC_AUTO) qr[i] = ch[i];
+        }
+        toff = (ce.blob.size() + 255) & ~(size_t)255;
+    }
+    Recorder rec;
+    pne_status rc = record_batch(rec, batch, hd, dA_base, db_base, dx_base, o, L, sk.data(), qr.data(), dinfo);
+    if (rc) return rc;
+    rc = (pne_status)build_groups(rec, &mainseq);
+    if (rc) return rc;
+    if (toff + mainseq.blob.size() > L.table_cap) return PNE_EWORKSPACE;
+    if (!mainseq.blob.empty()) {
+        HIP_OK(hipMemcpyAsync(L.tables + toff, mainseq.blob.data(), mainseq.blob.size(), hipMemcpyHostToDevice, st));
+        HIP_OK(hipStreamSynchronize(st));   // the host blobs are released on return
+    }
+    pne_batch_plan_s* plan = new (std::nothrow) pne_batch_plan_s;
+    if (!plan) return PNE_ENOMEM;
+    plan->batch = batch;
+    plan->dinfo = dinfo;
+    plan->dtables = L.tables;
+    plan->ce_groups = ce.groups;
+    plan->main_groups = mainseq.groups;
+    for (LaunchGroup& g : plan->main_groups) g.off += toff;
+    plan->tune = tp;
+    for (int64_t i = 0; i < batch; ++i)
+        if (precond_from_condest(L.prob[i], o, sk[i], qr[i])) plan->rerun_ce = true;
+    *out = plan;
+    return PNE_OK;
+}
+
+// Enqueues a plan: clear the info words, then every grouped launch (kernel
+// launches only).  run_ce = false skips the condition estimate (it has just
+// run at creation on the same data).
+pne_status plan_execute(pne_batch_plan_s* plan, hipStream_t st, bool run_ce)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(st, &cs) != hipSuccess) return PNE_EHIP;
+    const bool marks = cs == hipStreamCaptureStatusNone;
+    if (marks) {
+        prof_reset();
+        prof_mark(PH_START, st);
+    }
+    Exec ex0;
+    ex0.st = st;
+    zero_i32(ex0, plan->batch, plan->dinfo);
+    if (run_ce) enqueue_groups(plan->ce_groups, plan->dtables, st, false);
+    if (marks) prof_mark(PH_CONDEST, st);
+    enqueue_groups(plan->main_groups, plan->dtables, st, marks);
+    return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
 }
 
 pne_status solve_batched(int64_t batch, const pne_problem_desc* hd, const double* dA_base, const double* db_base,
@@ -461,35 +624,13 @@ pne_status solve_batched(int64_t batch, const pne_problem_desc* hd, const double
 {
     pne_status chk = check_batch(batch, hd, o, hpne);
     if (chk) return chk;
-    if (!dA_base || !db_base || !dx_base || !dinfo || !dwork) return PNE_EINVAL;
-    if (work_bytes < batched_size(batch, hd, o, hpne)) return PNE_EWORKSPACE;
-    BatchLayout L;
-    batch_layout(batch, hd, o, hpne, dwork, work_bytes, &L);
-    prof_reset();
-    prof_mark(PH_START, st);
-    Exec ex0;
-    ex0.st = st;
-    zero_i32(ex0, batch, dinfo);
-    std::vector<int32_t> sk(batch, o->sketch_prec), qr(batch, o->qr_prec);
-    if (batch_auto(o)) {
-        Recorder rec;
-        pne_status rc = record_condest(rec, batch, hd, dA_base, o, L);
-        if (rc) return rc;
-        rc = (pne_status)run_recorded(rec, L.tables, L.table_cap, st);
-        if (rc) return rc;
-        std::vector<int32_t> ch(batch);
-        HIP_OK(hipMemcpyAsync(ch.data(), L.choice, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_OK(hipStreamSynchronize(st));
-        for (int64_t i = 0; i < batch; ++i) {
-            if (sk[i] == PNE_PREC_AUTO) sk[i] = ch[i];
-            if (qr[i] == PNE_PREC_AUTO) qr[i] = ch[i];
-        }
-    }
-    prof_mark(PH_CONDEST, st);
-    Recorder rec;
-    pne_status rc = record_batch(rec, batch, hd, dA_base, db_base, dx_base, o, L, sk.data(), qr.data(), dinfo);
+    pne_batch_plan_s* plan = nullptr;
+    pne_status rc = plan_create(batch, hd, dA_base, db_base, dx_base, o, hpne, dwork, work_bytes, dinfo, st,
+                                batch_tune(batch, hd, o, hpne), &plan);
     if (rc) return rc;
-    return (pne_status)run_recorded(rec, L.tables, L.table_cap, st);
+    rc = plan_execute(plan, st, false);
+    delete plan;
+    return rc;
 }
 
 }  // namespace
@@ -530,6 +671,8 @@ void pne_default_opts(pne_opts* o)
     o->known_kappa = 0.0;
     o->refine_steps = 1;
     o->block_rows = 128;
+    o->cond_method = 0;
+    o->sketch_kind = 0;
 }
 
 const char* pne_status_string(pne_status st)
@@ -592,8 +735,10 @@ pne_status sketch_precond(int64_t m, int64_t n, const double* dA, int64_t lda, c
     float k0;
     pne_status rc = resolve_precision(ex, p, dA, o, b, scratch_cap_of(b), &sk, &qr, &k0);
     if (rc) return rc;
-    rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
-    if (rc) return rc;
+    if (!precond_from_condest(p, o, sk, qr)) {
+        rc = run_precond(ex, p, dA, o->seed, o->problem_id, sk, qr, b, dinfo);
+        if (rc) return rc;
+    }
     copy_f64(ex, n, n, b.R, n, dR, ldr);
     if (hipGetLastError() != hipSuccess) return PNE_EHIP;
     if (hinfo) {
@@ -623,6 +768,35 @@ pne_status cond_est(int64_t m, int64_t n, const double* dA, int64_t lda, float* 
     return (pne_status)condest_run(ex, m, n, dA, lda, 0.0, dkappa0, dchoice, dwork, work_bytes);
 }
 
+size_t cond_est_qr_workspace_size(int64_t m, int64_t n, int64_t s)
+{
+    if (n < 1 || m < n || n > 4096) return 0;
+    if (s == 0) s = 3 * n;
+    if (s < n || !qr_supported(s, PNE_PREC_FP32)) return 0;
+    Arena ar(nullptr, 0);
+    ar.take<float>((size_t)s * n);
+    ar.take<double>((size_t)n * n);
+    return ar.used + condest_qr_workspace_bytes(m, n, s);
+}
+
+pne_status cond_est_qr(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
+                       float* dkappa0, int32_t* dchoice, void* dwork, size_t work_bytes, pne_stream_t stream)
+{
+    if (!dA || !dkappa0 || !dchoice || !dwork) return PNE_EINVAL;
+    if (n < 1 || m < n || lda < m) return PNE_EINVAL;
+    if (s == 0) s = 3 * n;
+    if (s < n) return PNE_EINVAL;
+    if (n > 4096 || !qr_supported(s, PNE_PREC_FP32)) return PNE_ENOTSUP;
+    if (work_bytes < cond_est_qr_workspace_size(m, n, s)) return PNE_EWORKSPACE;
+    Arena ar(dwork, work_bytes);
+    float* W = ar.take<float>((size_t)s * n);
+    double* R = ar.take<double>((size_t)n * n);
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    return (pne_status)condest_qr_run(ex, m, n, dA, lda, s, seed, 0, dkappa0, dchoice, W, R, (char*)dwork + ar.used,
+                                      work_bytes - ar.used);
+}
+
 size_t pne_sketch_workspace_size(int64_t m, int64_t n, int64_t s, int32_t prec)
 {
     if (n < 1 || m < 1 || s < 1 || !valid_prec(prec, false, true)) return 0;
@@ -644,6 +818,26 @@ pne_status pne_sketch(int64_t m, int64_t n, const double* dA, int64_t lda, int64
     ex.st = (hipStream_t)stream;
     return (pne_status)sketch_run(ex, m, n, dA, lda, s, seed, problem_id, prec, br, nullptr, 0, dAs, ldas,
                                   dwork, work_bytes);
+}
+
+size_t pne_sketch_srft_workspace_size(int64_t m, int64_t n, int32_t prec)
+{
+    if (n < 1 || m < 1 || !srft_supported(prec)) return 0;
+    return srft_workspace_bytes(m, n, prec);
+}
+
+pne_status pne_sketch_srft(int64_t m, int64_t n, const double* dA, int64_t lda, int64_t s, uint64_t seed,
+                           uint32_t problem_id, int32_t prec, double* dAs, int64_t ldas, void* dwork,
+                           size_t work_bytes, pne_stream_t stream)
+{
+    if (!dA || !dAs || !dwork) return PNE_EINVAL;
+    if (n < 1 || m < 1 || s < 1 || lda < m || ldas < s) return PNE_EINVAL;
+    if (!srft_supported(prec)) return PNE_ENOTSUP;
+    if (work_bytes < srft_workspace_bytes(m, n, prec)) return PNE_EWORKSPACE;
+    Exec ex;
+    ex.st = (hipStream_t)stream;
+    return (pne_status)srft_run(ex, m, n, dA, lda, s, seed, problem_id, prec, nullptr, 0, dAs, ldas, dwork,
+                                work_bytes);
 }
 
 static Problem gram_problem(int64_t m, int64_t n, int64_t lda, int hpne)
@@ -688,7 +882,145 @@ pne_status pne_gram(int64_t m, int64_t n, const double* dA, int64_t lda, const d
 
 size_t pne_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* o, int hpne)
 {
+    if (check_batch(batch, hdesc, o, hpne) != PNE_OK) return 0;
+    TuneScope scope(batch_tune(batch, hdesc, o, hpne));
     return batched_size(batch, hdesc, o, hpne);
+}
+
+pne_status pne_batch_plan_create(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
+                                 const double* db_base, double* dx_base, const pne_opts* o, int hpne, void* dwork,
+                                 size_t work_bytes, int32_t* dinfo, pne_stream_t stream, pne_batch_plan* plan)
+{
+    if (!plan) return PNE_EINVAL;
+    *plan = nullptr;
+    pne_status chk = check_batch(batch, hdesc, o, hpne);
+    if (chk) return chk;
+    return plan_create(batch, hdesc, dA_base, db_base, dx_base, o, hpne, dwork, work_bytes, dinfo,
+                       (hipStream_t)stream, batch_tune(batch, hdesc, o, hpne), plan);
+}
+
+pne_status pne_batch_plan_execute(pne_batch_plan plan, pne_stream_t stream)
+{
+    if (!plan) return PNE_EINVAL;
+    return plan_execute(plan, (hipStream_t)stream, plan->rerun_ce);
+}
+
+pne_status pne_batch_plan_execute_graph(pne_batch_plan plan, pne_stream_t stream)
+{
+    if (!plan || !stream) return PNE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    if (!plan->gexec) {
+        hipGraph_t g = nullptr;
+        HIP_OK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        pne_status rc = plan_execute(plan, st, plan->rerun_ce);
+        const hipError_t e = hipStreamEndCapture(st, &g);
+        if (rc) {
+            if (g) (void)hipGraphDestroy(g);
+            return rc;
+        }
+        if (e != hipSuccess || !g) return PNE_EHIP;
+        const hipError_t ei = hipGraphInstantiate(&plan->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (ei != hipSuccess) {
+            plan->gexec = nullptr;
+            return PNE_EHIP;
+        }
+    }
+    HIP_OK(hipGraphLaunch(plan->gexec, st));
+    return PNE_OK;
+}
+
+void pne_batch_plan_destroy(pne_batch_plan plan) { delete plan; }
+
+// Candidate settings of the autotuner: the batch row chunk, the tile of the
+// short-K products (A R^-1, factor updates) and the order up to which
+// lower-triangle long-K products (the Gram matrices) use 64 x 64 tiles.
+static std::vector<TuneParams> tune_candidates()
+{
+    std::vector<TuneParams> c;
+    for (int64_t kc : {4096, 8192, 16384})
+        for (int st : {64, 128})
+            for (int ln : {512, 1024}) {
+                TuneParams p;
+                p.batch_kchunk = kc;
+                p.shortk_tile = st;
+                p.lower_small_n = ln;
+                c.push_back(p);
+            }
+    return c;
+}
+
+size_t pne_autotune_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* o,
+                                           int hpne)
+{
+    if (check_batch(batch, hdesc, o, hpne) != PNE_OK) return 0;
+    size_t best = 0;
+    for (const TuneParams& p : tune_candidates()) {
+        TuneScope scope(p);
+        const size_t b = batched_size(batch, hdesc, o, hpne);
+        if (b == 0) return 0;
+        if (b > best) best = b;
+    }
+    return best;
+}
+
+pne_status pne_autotune_batched(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,
+                                const double* db_base, double* dx_base, const pne_opts* o, int hpne, void* dwork,
+                                size_t work_bytes, int32_t* dinfo, pne_stream_t stream, pne_tune_result* result)
+{
+    pne_status chk = check_batch(batch, hdesc, o, hpne);
+    if (chk) return chk;
+    if (!dA_base || !db_base || !dx_base || !dinfo || !dwork) return PNE_EINVAL;
+    hipStream_t st = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    HIP_OK(hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return PNE_EHIP;
+    }
+    TuneParams best;
+    double best_ms = -1.0;
+    pne_status rc = PNE_OK;
+    for (const TuneParams& p : tune_candidates()) {
+        pne_batch_plan_s* plan = nullptr;
+        rc = plan_create(batch, hdesc, dA_base, db_base, dx_base, o, hpne, dwork, work_bytes, dinfo, st, p, &plan);
+        if (rc == PNE_EWORKSPACE) { rc = PNE_OK; continue; }   // needs more than the caller gave
+        if (rc) break;
+        // one warm-up execution, then the median of three timed ones
+        rc = plan_execute(plan, st, plan->rerun_ce);
+        double t[3] = {0, 0, 0};
+        for (int k = 0; k < 3 && !rc; ++k) {
+            if (hipEventRecord(e0, st) != hipSuccess) { rc = PNE_EHIP; break; }
+            rc = plan_execute(plan, st, plan->rerun_ce);
+            if (rc) break;
+            float ms = 0.0f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { rc = PNE_EHIP; break; }
+            t[k] = ms;
+        }
+        delete plan;
+        if (rc) break;
+        if (t[0] > t[1]) { double x = t[0]; t[0] = t[1]; t[1] = x; }
+        if (t[1] > t[2]) { double x = t[1]; t[1] = t[2]; t[2] = x; }
+        if (t[0] > t[1]) { double x = t[0]; t[0] = t[1]; t[1] = x; }
+        if (best_ms < 0.0 || t[1] < best_ms) { best_ms = t[1]; best = p; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc) return rc;
+    if (best_ms < 0.0) return PNE_EWORKSPACE;
+    double sn = 0.0, sm = 0.0;
+    for (int64_t i = 0; i < batch; ++i) { sn += (double)hdesc[i].n; sm += (double)hdesc[i].m; }
+    const bool stored = tune_store(tune_key_batched(hpne, o->sketch_prec, o->qr_prec, batch, sn / batch, sm / batch),
+                                   best, best_ms);
+    if (result) {
+        result->batch_kchunk = best.batch_kchunk;
+        result->shortk_tile = best.shortk_tile;
+        result->lower_small_n = best.lower_small_n;
+        result->ms = best_ms;
+        result->stored = stored ? 1 : 0;
+    }
+    return PNE_OK;
 }
 
 pne_status pne_solve_batched(int64_t batch, const pne_problem_desc* hdesc, const double* dA_base,

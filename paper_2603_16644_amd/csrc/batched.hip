@@ -10,8 +10,9 @@
 // member's step is small (QR panels, triangular blocks, solves).
 //
 // The group tables (first work-group, grid width and arguments per member)
-// are built on the host, copied once into the caller's workspace, and the
-// launches are then enqueued back to back on the stream.
+// are built on the host and copied once into the caller's workspace; the
+// launches are then enqueued back to back on the stream, as often as a plan
+// is executed (kernel launches only: capturable into a hipGraph).
 #include <algorithm>
 #include <vector>
 
@@ -23,14 +24,6 @@
 namespace pne {
 
 namespace {
-
-struct Group {
-    GroupLaunchFn fn;
-    size_t off;
-    int count;
-    int64_t total;
-    uint32_t stage;
-};
 
 // Profile phase that ends with a stage (see profile.h).
 int stage_phase(uint32_t st)
@@ -52,7 +45,7 @@ int stage_phase(uint32_t st)
 
 }  // namespace
 
-int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st)
+int build_groups(const Recorder& rec, GroupSeq* out)
 {
     const std::vector<LaunchRec>& R = rec.recs;
     std::vector<uint32_t> idx(R.size());
@@ -62,8 +55,10 @@ int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st)
         if (R[a].fn != R[b].fn) return (uintptr_t)R[a].fn < (uintptr_t)R[b].fn;
         return R[a].member < R[b].member;
     });
-    std::vector<char> blob;
-    std::vector<Group> groups;
+    std::vector<char>& blob = out->blob;
+    std::vector<LaunchGroup>& groups = out->groups;
+    blob.clear();
+    groups.clear();
     size_t i = 0;
     while (i < idx.size()) {
         size_t j = i + 1;
@@ -86,20 +81,34 @@ int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st)
         }
         if (total >= ((int64_t)1 << 31)) return PNE_ENOTSUP;
         start[count] = (int32_t)total;
-        groups.push_back(Group{r0.fn, off, count, total, (uint32_t)(r0.key >> 56)});
+        groups.push_back(LaunchGroup{r0.fn, off, count, total, (uint32_t)(r0.key >> 56)});
         i = j;
     }
-    if (blob.empty()) return PNE_OK;
-    if (blob.size() > cap || !dtables) return PNE_EWORKSPACE;
-    // the host blob is released on return: wait for the copy
-    HIP_OK(hipMemcpyAsync(dtables, blob.data(), blob.size(), hipMemcpyHostToDevice, st));
-    HIP_OK(hipStreamSynchronize(st));
+    return PNE_OK;
+}
+
+void enqueue_groups(const std::vector<LaunchGroup>& groups, const char* dtables, hipStream_t st, bool marks)
+{
     for (size_t g = 0; g < groups.size(); ++g) {
-        const Group& G = groups[g];
+        const LaunchGroup& G = groups[g];
         G.fn(dtables + G.off, G.count, G.total, st);
+        if (!marks) continue;
         const bool last = g + 1 == groups.size();
         if (last || stage_phase(groups[g + 1].stage) != stage_phase(G.stage)) prof_mark(stage_phase(G.stage), st);
     }
+}
+
+int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st)
+{
+    GroupSeq seq;
+    int rc = build_groups(rec, &seq);
+    if (rc) return rc;
+    if (seq.blob.empty()) return PNE_OK;
+    if (seq.blob.size() > cap || !dtables) return PNE_EWORKSPACE;
+    // the host blob is released on return: wait for the copy
+    HIP_OK(hipMemcpyAsync(dtables, seq.blob.data(), seq.blob.size(), hipMemcpyHostToDevice, st));
+    HIP_OK(hipStreamSynchronize(st));
+    enqueue_groups(seq.groups, dtables, st, true);
     return hipGetLastError() == hipSuccess ? PNE_OK : PNE_EHIP;
 }
 

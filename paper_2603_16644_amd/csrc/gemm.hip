@@ -14,6 +14,7 @@
 // kernel reduces in a fixed order.
 #include "common.h"
 #include "kernels.h"
+#include "tune.h"
 #include "launch.h"
 
 namespace pne {
@@ -336,10 +337,13 @@ __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
 struct TileShape {
     int bm, bn;
 };
+// (The 64 / 512 choices are the defaults of TuneParams; the autotuner may
+// replace them per workload, see tune.h.)
 static TileShape tile_shape(int64_t, int64_t N, int64_t K, int lower)
 {
-    if (K < 4096) return TileShape{64, 64};
-    if (lower) return N <= 512 ? TileShape{64, 64} : TileShape{128, 128};
+    const TuneParams& tp = tune_params();
+    if (K < 4096) return tp.shortk_tile == 128 ? TileShape{128, 128} : TileShape{64, 64};
+    if (lower) return N <= tp.lower_small_n ? TileShape{64, 64} : TileShape{128, 128};
     return N <= 64 ? TileShape{128, 64} : TileShape{128, 128};
 }
 

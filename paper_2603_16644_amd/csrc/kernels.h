@@ -48,6 +48,14 @@ int sketch_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int
                uint32_t pid, int prec, int64_t br, float* As32, int64_t ld32, double* As64,
                int64_t ld64, void* work, size_t work_bytes);
 
+// SRFT sketch (srft.hip): A_s = (1/sqrt(s)) S H D A with the Hartley
+// transform of length srft_padded_length(m); precisions FP64, FP32, BF16.
+int64_t srft_padded_length(int64_t m);
+bool srft_supported(int prec);
+size_t srft_workspace_bytes(int64_t m, int64_t n, int prec);
+int srft_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed, uint32_t pid,
+             int prec, float* As32, int64_t ld32, double* As64, int64_t ld64, void* work, size_t work_bytes);
+
 // ---------------------------------------------------------------- GEMM
 // Column-major C = alpha op(A) op(B) + beta Cin (C may alias Cin).
 // With splits > 1 the raw products go to partial buffers P[z] (M x N, ld M)
@@ -125,6 +133,12 @@ void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const doubl
                   double* y, int32_t* flags, int32_t* info);   // y: n-vector scratch (L^T y = z)
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
                  const double* DU, const double* c, double* x, int32_t* flags, int32_t* info);
+// x = U^{-1} c (U upper, DU the inverses of its 64 x 64 diagonal blocks);
+// flags: lb_flag_words(n) int32; c and x may alias.
+void upper_solve_lb(Exec& ex, int64_t n, const double* U, int64_t ld, const double* DU, const double* c, double* x,
+                    int32_t* flags, int32_t* info);
+// *info = 1000 + k + 1 for the first zero or non-finite R(k, k) (if still 0)
+void check_r_diag(Exec& ex, int64_t n, const double* R, int64_t ldr, int32_t* info);
 // out (c x r, ldo) = in^T (in r x c, ldi)
 void transpose_f64(Exec& ex, int64_t r, int64_t c, const double* in, int64_t ldi, double* out, int64_t ldo);
 // transposes of the 64 x 64 blocks of a block-inverse array (dinv_elems(n))
@@ -145,14 +159,39 @@ void zero_i32(Exec& ex, int64_t n, int32_t* p);
 void copy_i32(Exec& ex, int64_t n, const int32_t* src, int32_t* dst);
 
 // ---------------------------------------------------------------- batches
-// Merge the recorded launches of a batch into grouped launches, copy their
-// tables to dtables (cap bytes) and enqueue them on st (batched.hip).
+// One grouped launch: the kernel, its table at byte offset `off` of the
+// device table area, the member count, the total work-group count and the
+// pipeline stage (for phase marks).
+struct LaunchGroup {
+    GroupLaunchFn fn;
+    size_t off;
+    int count;
+    int64_t total;
+    uint32_t stage;
+};
+struct GroupSeq {
+    std::vector<char> blob;             // host copy of the group tables
+    std::vector<LaunchGroup> groups;    // in launch order
+};
+// Merge the recorded launches of a batch into grouped launches (host only).
+int build_groups(const Recorder& rec, GroupSeq* out);
+// Enqueue grouped launches whose tables sit at dtables (kernel launches
+// only; phase marks when `marks`).
+void enqueue_groups(const std::vector<LaunchGroup>& groups, const char* dtables, hipStream_t st, bool marks);
+// build_groups, copy the tables to dtables (cap bytes; one wait for the
+// copy) and enqueue them on st (batched.hip).
 int run_recorded(const Recorder& rec, char* dtables, size_t cap, hipStream_t st);
 
 // ---------------------------------------------------------------- condition estimate
 size_t condest_workspace_bytes(int64_t m, int64_t n, int64_t kchunk_fixed = 0);
 int condest_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, double known_kappa, float* dk0,
                 int32_t* dchoice, void* work, size_t work_bytes);
+// estimate from the FP32 QR of the FP32 sketch (s rows, seed, pid); W (s x n
+// FP32, ld s) and R (n x n FP64) receive the sketch and its R factor
+size_t condest_qr_workspace_bytes(int64_t m, int64_t n, int64_t s, int64_t kchunk_fixed = 0);
+int condest_qr_run(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, int64_t s, uint64_t seed,
+                   uint32_t pid, float* dk0, int32_t* dchoice, float* W, double* R, void* work,
+                   size_t work_bytes);
 
 // ---------------------------------------------------------------- single solves (api.hip)
 // workspace bytes of one PNE (hpne = 0) / HPNE (hpne = 1) solve, after the

@@ -876,6 +876,11 @@ static int qr_run(Exec& ex, int64_t s, int64_t n, T* W, int64_t ldw, int prec, d
     return launch_status(ex);
 }
 
+void check_r_diag(Exec& ex, int64_t n, const double* R, int64_t ldr, int32_t* info)
+{
+    launch<RDiagCheck>(ex, 1, 1, RDiagCheck::Args{n, R, ldr, info});
+}
+
 int qr_r(Exec& ex, int64_t s, int64_t n, void* W, int64_t ldw, int prec, double* R, int64_t ldr,
          int32_t* info, void* work, size_t work_bytes)
 {

@@ -270,6 +270,14 @@ void pne_solve_lb(Exec& ex, int64_t n, const double* L, int64_t ldl, const doubl
     launch<TrsvLB2>(ex, 2 * nb, 1, TrsvLB2::Args{s1, s2, flags + fw});
 }
 
+void upper_solve_lb(Exec& ex, int64_t n, const double* U, int64_t ld, const double* DU, const double* c, double* x,
+                    int32_t* flags, int32_t* info)
+{
+    zero_i32(ex, (int64_t)lb_flag_words(n), flags);
+    if (c != x) copy_f64(ex, n, 1, c, n, x, n);
+    trsv_lb(ex, n, U, ld, 0, DU, x, flags, info);
+}
+
 void lu_solve_lb(Exec& ex, int64_t n, const double* LU, int64_t ld, const int32_t* piv, const double* DL,
                  const double* DU, const double* c, double* x, int32_t* flags, int32_t* info)
 {

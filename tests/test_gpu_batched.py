@@ -105,6 +105,85 @@ def test_batched_singular_member_is_isolated(pne):
     assert np.all(np.isfinite(xb[:50])) and np.all(np.isnan(xb[50:90]))
 
 
+# ------------------------------------------------------------------ plans, graphs, autotuner
+
+def test_plan_executions_match_one_shot_call(pne, small_batch):
+    """A plan executed twice gives the one-shot batched call's x bit for bit
+    (same grouped launches; the info words and flags are cleared by kernels
+    at every execution)."""
+    probs, _ = small_batch
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=5, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    pne.pne_solve_batched(A, b, x, descs, opts=o)
+    ref = host(x).copy()
+    plan = pne.BatchPlan(A, b, x, descs, opts=o)
+    for _ in range(2):
+        x.zero_()
+        info = plan.execute()
+        assert np.all(host(info) == 0)
+        assert np.array_equal(host(x), ref)
+    plan.close()
+
+
+@pytest.mark.parametrize("auto", [False, True])
+def test_plan_graph_replays_match_uncaptured(pne, small_batch, auto):
+    """The plan captured into a hipGraph and replayed three times, with other
+    eager work and host synchronisations between the replays: every replay
+    matches the uncaptured execution bit for bit."""
+    probs, _ = small_batch
+    A, b, x, descs = pack(probs)
+    if auto:
+        o = pne.make_opts(seed=6, sketch_prec="auto", qr_prec="auto", refine_steps=1, cond_method=1)
+    else:
+        o = pne.make_opts(seed=6, sketch_prec="fp16", qr_prec="fp16", refine_steps=2)
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan = pne.BatchPlan(A, b, x, descs, opts=o, stream=st)
+        plan.execute(stream=st)
+        st.synchronize()
+        ref = host(x).copy()
+        for k in range(3):
+            x.fill_(float("nan"))
+            junk = torch.randn(1 << 20, device="cuda").sum()        # unrelated eager work
+            info = plan.execute_graph(st)
+            st.synchronize()
+            assert float(junk) == float(junk)
+            assert np.all(host(info) == 0)
+            assert np.array_equal(host(x), ref), k
+    plan.close()
+
+
+def test_autotuner_stores_and_reuses_parameters(pne, small_batch, tmp_path, monkeypatch):
+    """The autotuner times its candidates on the batch, stores the fastest in
+    $PNE_TUNE_CACHE; later batched calls of the same workload read it back
+    (their results equal a plan built with the stored parameters) and stay
+    accurate."""
+    import json
+    probs, err_qr = small_batch
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PNE_TUNE_CACHE", str(cache))
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=7, sketch_prec="bf16", qr_prec="fp32", refine_steps=2)
+    res = pne.autotune_batched(A, b, x, descs, opts=o)
+    assert res["stored"] and res["ms"] > 0
+    assert res["batch_kchunk"] in (4096, 8192, 16384) and res["shortk_tile"] in (64, 128)
+    data = json.loads(cache.read_text())
+    assert len(data) == 1
+    (key, entry), = data.items()
+    assert key.startswith("batched/pne/sk4/qr2/") and entry["batch_kchunk"] == res["batch_kchunk"]
+    x.zero_()
+    info = pne.pne_solve_batched(A, b, x, descs, opts=o)
+    assert np.all(host(info) == 0)
+    xb = host(x).copy()
+    plan = pne.BatchPlan(A, b, x, descs, opts=o)
+    x.zero_()
+    plan.execute()
+    assert np.array_equal(host(x), xb)
+    plan.close()
+    for i, (p, d) in enumerate(zip(probs, descs)):
+        assert relerr(xb[d["x_offset"]:d["x_offset"] + p.n], p.numpy_x_star()) <= 10 * err_qr[i]
+
+
 # ------------------------------------------------------------------ 512 problems
 
 def test_batch512_known_solutions(pne):
@@ -130,6 +209,18 @@ def test_batch512_known_solutions(pne):
         if not e <= 10 * bound:
             bad.append((i, p.m, p.n, p.kappa, p.rho, e, bound))
     assert not bad, bad[:10]
+    # the same batch as a plan captured into a hipGraph: two replays match
+    # the uncaptured call bit for bit
+    st = torch.cuda.Stream()
+    with torch.cuda.stream(st):
+        plan = pne.BatchPlan(A, b, x, descs, opts=o, stream=st)
+        for k in range(2):
+            x.fill_(float("nan"))
+            info = plan.execute_graph(st)
+            st.synchronize()
+            assert np.all(host(info) == 0)
+            assert np.array_equal(host(x), xb), k
+        plan.close()
 
 
 def test_batch512_sampled_members_within_qr_error(pne):
