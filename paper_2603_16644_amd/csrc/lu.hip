@@ -43,10 +43,12 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
     double* __restrict__ P = a.P;
     int32_t* __restrict__ piv = a.piv;
     int32_t* __restrict__ info = a.info;
-    __shared__ double rowK[PW], rowP[PW];
-    __shared__ double wv[LU_WAVES];
-    __shared__ int64_t wi[LU_WAVES];
-    __shared__ int64_t pivsh;
+    // rows k and p and the wavefront argmax candidates, double-buffered by
+    // the parity of k: step k + 1 never overwrites what a slower thread of
+    // step k still reads, so each column needs two barriers
+    __shared__ double rowK[2][PW], rowP[2][PW];
+    __shared__ double wv[2][LU_WAVES];
+    __shared__ int64_t wi[2][LU_WAVES];
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double x[RPT][PW];
 #pragma unroll
@@ -56,6 +58,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
         for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
     }
     for (int k = 0; k < w; ++k) {
+        const int B = k & 1;
         // argmax |x(r, k)| over r >= k, first index on ties; a NaN counts as
         // +inf, so a column holding one selects a non-finite pivot
         double best = -1.0;
@@ -76,29 +79,25 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             const int64_t oi = __shfl_xor(bidx, off, 64);
             if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
-        if (lane == 0) { wv[wid] = best; wi[wid] = bidx; }
+        if (lane == 0) { wv[B][wid] = best; wi[B][wid] = bidx; }
         __syncthreads();
-        if (tid == 0) {
-            double b = wv[0];
-            int64_t bi = wi[0];
-            for (int i = 1; i < LU_WAVES; ++i)
-                if (wv[i] > b || (wv[i] == b && wi[i] < bi)) { b = wv[i]; bi = wi[i]; }
-            if (bi < k || bi >= h) bi = k;   // no candidate: keep the row in place
-            pivsh = bi;
-            piv[c0 + k] = (int32_t)(c0 + bi);
-        }
-        __syncthreads();
-        const int64_t p = pivsh;
-        // exchange rows k and p of the panel
+        // every thread forms the pivot row from the candidates
+        double b = wv[B][0];
+        int64_t p = wi[B][0];
+        for (int i = 1; i < LU_WAVES; ++i)
+            if (wv[B][i] > b || (wv[B][i] == b && wi[B][i] < p)) { b = wv[B][i]; p = wi[B][i]; }
+        if (p < k || p >= h) p = k;   // no candidate: keep the row in place
+        if (tid == 0) piv[c0 + k] = (int32_t)(c0 + p);
+        // publish rows k and p of the panel
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
             if (r == p)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) rowP[c] = x[q][c];
+                for (int c = 0; c < PW; ++c) rowP[B][c] = x[q][c];
             if (r == k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) rowK[c] = x[q][c];
+                for (int c = 0; c < PW; ++c) rowK[B][c] = x[q][c];
         }
         __syncthreads();
 #pragma unroll
@@ -106,15 +105,15 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             const int64_t r = tid + LU_THREADS * q;
             if (r == k && p != k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) x[q][c] = rowP[c];
+                for (int c = 0; c < PW; ++c) x[q][c] = rowP[B][c];
             if (r == p && p != k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) x[q][c] = rowK[c];
+                for (int c = 0; c < PW; ++c) x[q][c] = rowK[B][c];
         }
         double pv = 0.0;
 #pragma unroll
         for (int c = 0; c < PW; ++c)
-            if (c == k) pv = rowP[c];
+            if (c == k) pv = rowP[B][c];
         if (pv == 0.0 || !isfinite(pv)) {
             if (tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
         } else {
@@ -122,17 +121,21 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             for (int q = 0; q < RPT; ++q) {
                 const int64_t r = tid + LU_THREADS * q;
                 if (r > k && r < h) {
-                    double l = 0.0;
+                    // select x(r, k) first: a division inside the selection
+                    // would be evaluated for every column
+                    double xk = 0.0;
 #pragma unroll
                     for (int c = 0; c < PW; ++c)
-                        if (c == k) { l = x[q][c] / pv; x[q][c] = l; }
+                        if (c == k) xk = x[q][c];
+                    const double l = xk / pv;
 #pragma unroll
-                    for (int c = 0; c < PW; ++c)
-                        if (c > k) x[q][c] -= l * rowP[c];
+                    for (int c = 0; c < PW; ++c) {
+                        if (c == k) x[q][c] = l;
+                        if (c > k) x[q][c] -= l * rowP[B][c];
+                    }
                 }
             }
         }
-        __syncthreads();
     }
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {

@@ -412,6 +412,7 @@ static int srft_run_t(Exec& ex, const SrftPlan& p, int64_t m, int64_t n, const d
                           1.0 / sqrt((double)s), As32, As64, As64 ? ld64 : ld32};
         launch<SrftSample<T>>(ex, ceil_div(s * P, 256), 1, sa);
     }
+    if (!ex.recording()) prof_mark(PH_SK_GEMM, ex.st);   // the whole SRFT counts as the sketch product
     return launch_status(ex);
 }
 
