@@ -1,13 +1,13 @@
 // LU factorization with partial pivoting P C = L U of the n x n HPNE matrix
 // A_p^T A (Section 1, eq. e_hpne; the system is non-symmetric).  Blocked,
 // right-looking:
-//   panel (PW columns, all rows below): one 512-thread work-group with the
-//     panel in registers; per column the pivot is the first row of largest
-//     magnitude (wavefront argmax, ties to the smaller index), the two rows
-//     are exchanged through LDS, the column is scaled and the rest of the
-//     panel gets the rank-1 update;
-//   the same row exchanges are applied to the other columns;
-//   U12 := L11^{-1} C12 (unit lower, row-parallel leaf on U12^T);
+//   panel (PW = 32, 16 or 8 columns, all rows below), one 512-thread work-group:
+//     the panel in registers; per column the pivot is the first row of
+//     largest magnitude (wavefront argmax, ties to the smaller index), the
+//     two rows are exchanged through LDS, the column is scaled and the rest
+//     of the panel gets the rank-1 update; then, in the same kernel, the row
+//     exchanges are applied to the other columns and U12 := L11^{-1} C12
+//     (unit lower forward substitution, one thread per column);
 //   C22 -= L21 U12 (MFMA GEMM).
 // A zero or non-finite pivot at global column k sets *info = 3000 + k + 1
 // (first only); that column's elimination is skipped.
@@ -20,10 +20,30 @@ namespace pne {
 constexpr int LU_THREADS = 512;
 constexpr int LU_WAVES = LU_THREADS / 64;
 
+// Shared state of the panel kernel.  Rows k and p and the per-wavefront
+// argmax candidates are double-buffered by the parity of the step, so step
+// k + 1 never overwrites what a slower thread of step k still reads.
+template <int PW>
+struct LuShared {
+    double rowK[2][PW], rowP[2][PW], rowPu[2][PW];
+    double wv[2][LU_WAVES];
+    int64_t wi[2][LU_WAVES];
+    int32_t pivl[PW];              // pivot rows of the panel (relative to its first row)
+    double L11[PW][PW + 1];        // unit lower triangle of the factored panel's top rows
+};
+
+// One panel step of the blocked LU in one 512-thread work-group:
+//   1. factor the panel C(c0:n, c0:c0+w) in registers (partial pivoting);
+//   2. apply its row exchanges to every other column;
+//   3. U12 := L11^{-1} C12 for the columns right of the panel (unit lower
+//      forward substitution, L11 from LDS; one thread per column).
+// Steps 2 and 3 take one column per thread at a time; a column's exchanges
+// precede its substitution.  The trailing update C22 -= L21 U12 follows as
+// an MFMA GEMM launch.
 struct LuPanelArgs {
-    int64_t h;
+    int64_t n;
     int w;
-    double* P;
+    double* C;
     int64_t ldc;
     int32_t* piv;
     int64_t c0;
@@ -38,18 +58,15 @@ struct LuPanel {
 template <int RPT, int PW>
 __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 {
-    const int64_t h = a.h, ldc = a.ldc, c0 = a.c0;
+    const int64_t n = a.n, ldc = a.ldc, c0 = a.c0, h = n - c0;
     const int w = a.w;
-    double* __restrict__ P = a.P;
-    int32_t* __restrict__ piv = a.piv;
+    double* __restrict__ C = a.C;
+    double* __restrict__ P = C + c0 + c0 * ldc;
+    __shared__ LuShared<PW> sh;
+    __shared__ double colL[PW * LU_THREADS];   // column segments of the U12 substitution
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, wid = tid >> 6;
     int32_t* __restrict__ info = a.info;
-    // rows k and p and the wavefront argmax candidates, double-buffered by
-    // the parity of k: step k + 1 never overwrites what a slower thread of
-    // step k still reads, so each column needs two barriers
-    __shared__ double rowK[2][PW], rowP[2][PW];
-    __shared__ double wv[2][LU_WAVES];
-    __shared__ int64_t wi[2][LU_WAVES];
-    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     double x[RPT][PW];
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
@@ -57,6 +74,15 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
         for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
     }
+    // Column step k.  The register array is rotated left by one column
+    // after every step, so the active column is always x[.][0] and every
+    // register index is a compile-time constant; after step k the columns
+    // already factored sit at the end (positions PW - k .. PW - 1).  Two
+    // barriers per step: after the wavefront argmax candidates are published
+    // (every thread then forms the pivot row itself) and after the owners of
+    // rows k and p publish them.  The owner of the pivot row also publishes
+    // it with the factored columns zeroed (rowPu), which the rank-1 update
+    // uses, so that no thread tests column positions.
     for (int k = 0; k < w; ++k) {
         const int B = k & 1;
         // argmax |x(r, k)| over r >= k, first index on ties; a NaN counts as
@@ -66,10 +92,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
-            double v = -1.0;
-#pragma unroll
-            for (int c = 0; c < PW; ++c)
-                if (c == k) v = fabs(x[q][c]);
+            double v = fabs(x[q][0]);
             if (v != v) v = INFINITY;
             if (r >= k && r < h && v > best) { best = v; bidx = r; }
         }
@@ -79,100 +102,91 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             const int64_t oi = __shfl_xor(bidx, off, 64);
             if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
         }
-        if (lane == 0) { wv[B][wid] = best; wi[B][wid] = bidx; }
+        if (lane == 0) { sh.wv[B][wid] = best; sh.wi[B][wid] = bidx; }
         __syncthreads();
-        // every thread forms the pivot row from the candidates
-        double b = wv[B][0];
-        int64_t p = wi[B][0];
+        double bb = sh.wv[B][0];
+        int64_t p = sh.wi[B][0];
         for (int i = 1; i < LU_WAVES; ++i)
-            if (wv[B][i] > b || (wv[B][i] == b && wi[B][i] < p)) { b = wv[B][i]; p = wi[B][i]; }
+            if (sh.wv[B][i] > bb || (sh.wv[B][i] == bb && sh.wi[B][i] < p)) { bb = sh.wv[B][i]; p = sh.wi[B][i]; }
         if (p < k || p >= h) p = k;   // no candidate: keep the row in place
-        if (tid == 0) piv[c0 + k] = (int32_t)(c0 + p);
-        // publish rows k and p of the panel
+        if (tid == 0) sh.pivl[k] = (int32_t)p;
+        const int live = PW - k;      // positions 0 .. live - 1 are not factored yet
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
             if (r == p)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) rowP[B][c] = x[q][c];
+                for (int c = 0; c < PW; ++c) {
+                    sh.rowP[B][c] = x[q][c];
+                    sh.rowPu[B][c] = c < live ? x[q][c] : 0.0;
+                }
             if (r == k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) rowK[B][c] = x[q][c];
+                for (int c = 0; c < PW; ++c) sh.rowK[B][c] = x[q][c];
         }
         __syncthreads();
+        const double pv = sh.rowP[B][0];
+        const bool ok = pv != 0.0 && isfinite(pv);
+        if (!ok && tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
+            // exchange rows k and p
             if (r == k && p != k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) x[q][c] = rowP[B][c];
+                for (int c = 0; c < PW; ++c) x[q][c] = sh.rowP[B][c];
             if (r == p && p != k)
 #pragma unroll
-                for (int c = 0; c < PW; ++c) x[q][c] = rowK[B][c];
-        }
-        double pv = 0.0;
+                for (int c = 0; c < PW; ++c) x[q][c] = sh.rowK[B][c];
+            // multiplier and rank-1 update of the rows below k
+            if (ok && r > k && r < h) {
+                const double l = x[q][0] / pv;
+                x[q][0] = l;
 #pragma unroll
-        for (int c = 0; c < PW; ++c)
-            if (c == k) pv = rowP[B][c];
-        if (pv == 0.0 || !isfinite(pv)) {
-            if (tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
-        } else {
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int64_t r = tid + LU_THREADS * q;
-                if (r > k && r < h) {
-                    // select x(r, k) first: a division inside the selection
-                    // would be evaluated for every column
-                    double xk = 0.0;
-#pragma unroll
-                    for (int c = 0; c < PW; ++c)
-                        if (c == k) xk = x[q][c];
-                    const double l = xk / pv;
-#pragma unroll
-                    for (int c = 0; c < PW; ++c) {
-                        if (c == k) x[q][c] = l;
-                        if (c > k) x[q][c] -= l * rowP[B][c];
-                    }
-                }
+                for (int c = 1; c < PW; ++c) x[q][c] -= l * sh.rowPu[B][c];
             }
+            // rotate: the factored column moves to the end
+            const double x0 = x[q][0];
+#pragma unroll
+            for (int c = 0; c < PW - 1; ++c) x[q][c] = x[q][c + 1];
+            x[q][PW - 1] = x0;
         }
     }
+    // position c now holds panel column (c + w) mod PW
 #pragma unroll
     for (int q = 0; q < RPT; ++q) {
         const int64_t r = tid + LU_THREADS * q;
-        if (r < h)
 #pragma unroll
-            for (int c = 0; c < PW; ++c)
-                if (c < w) P[r + c * ldc] = x[q][c];
+        for (int c = 0; c < PW; ++c) {
+            int col = c + w;
+            if (col >= PW) col -= PW;
+            if (r < h && col < w) P[r + col * ldc] = x[q][c];
+            if (r < w) sh.L11[r][col] = (col < r) ? x[q][c] : 0.0;
+        }
     }
-}
-
-// Apply the panel's row exchanges to every column outside [c0, c0 + w).
-struct LuSwap {
-    struct Args {
-        int64_t n;
-        double* C;
-        int64_t ldc;
-        const int32_t* piv;
-        int64_t c0;
-        int w;
-    };
-    static constexpr int NTH = 256, WPE = 0;
-    static __device__ void run(const Args& a, int bx, int by);
-};
-__device__ void LuSwap::run(const Args& a, int bx, int)
-{
-    const int64_t n = a.n, ldc = a.ldc, c0 = a.c0;
-    const int w = a.w;
-    double* __restrict__ C = a.C;
-    const int32_t* __restrict__ piv = a.piv;
-    const int64_t j = (int64_t)bx * 256 + threadIdx.x;
-    if (j >= n || (j >= c0 && j < c0 + w)) return;
-    double* col = C + j * ldc;
-    for (int k = 0; k < w; ++k) {
-        const int64_t p = piv[c0 + k];
-        const int64_t r = c0 + k;
-        if (p != r) { double t = col[r]; col[r] = col[p]; col[p] = t; }
+    __syncthreads();
+    if (tid < w) a.piv[c0 + tid] = (int32_t)(c0 + sh.pivl[tid]);
+    for (int64_t j = tid; j < n; j += LU_THREADS) {
+        if (j >= c0 && j < c0 + w) continue;
+        double* col = C + j * ldc + c0;
+        for (int k = 0; k < w; ++k) {
+            const int64_t pk = sh.pivl[k];
+            if (pk != k) { const double t = col[k]; col[k] = col[pk]; col[pk] = t; }
+        }
+        if (j >= c0 + w) {
+            // forward substitution with the unit lower L11 on this thread's
+            // column segment, staged in LDS (element i of thread t at
+            // i * threads + t: conflict-free) with run-time loops, so that no
+            // register array is indexed
+            double* u = colL + tid;
+            for (int i = 0; i < w; ++i) u[i * LU_THREADS] = col[i];
+            for (int i = 1; i < w; ++i) {
+                double v = u[i * LU_THREADS];
+                for (int l = 0; l < i; ++l) v -= sh.L11[i][l] * u[l * LU_THREADS];
+                u[i * LU_THREADS] = v;
+            }
+            for (int i = 0; i < w; ++i) col[i] = u[i * LU_THREADS];
+        }
     }
 }
 
@@ -181,19 +195,13 @@ static void lu_steps(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, 
 {
     ex.iter((uint32_t)c0);
     const int w = (int)((n - c0 < PW) ? n - c0 : PW);
-    const int64_t h = n - c0;
-    launch<LuPanel<RPT, PW>>(ex, 1, 1, LuPanelArgs{h, w, C + c0 + c0 * ldc, ldc, piv, c0, info});
-    launch<LuSwap>(ex, ceil_div(n, 256), 1, LuSwap::Args{n, C, ldc, piv, c0, w});
+    launch<LuPanel<RPT, PW>>(ex, 1, 1, LuPanelArgs{n, w, C, ldc, piv, c0, info});
     const int64_t rem = n - c0 - w;
     if (rem <= 0) return;
-    double* C12 = C + c0 + (c0 + w) * ldc;
-    // U12^T L11^T = C12^T: row j of U12^T is column j of C12 (stride 1 along
-    // the row, ldc between rows)
-    trsm_leaf<double, true, true>(ex, rem, w, C12, ldc, 1, C + c0 + c0 * ldc, ldc);
     GemmArgs g{};
     g.M = rem; g.N = rem; g.K = w;
     g.A = C + (c0 + w) + c0 * ldc; g.lda = ldc; g.transA = 0;
-    g.B = C12; g.ldb = ldc; g.transB = 0;
+    g.B = C + c0 + (c0 + w) * ldc; g.ldb = ldc; g.transB = 0;
     g.alpha = -1.0; g.beta = 1.0;
     double* C22 = C + (c0 + w) + (c0 + w) * ldc;
     g.Cin = C22; g.ldcin = ldc; g.C = C22; g.ldc = ldc;
