@@ -37,6 +37,17 @@ U64 = 2.0 ** -53
 COPY_PROBE_BYTES = 512 << 20   # read once and written once by the copy probe
 
 
+# --only: name -> (solver, options of make_opts); solver "qr" is qr_ls_solve
+ONLY_CASES = {
+    "mixed_pne": ("pne", dict(sketch_prec="bf16", qr_prec="fp32", refine_steps=1)),
+    "mixed_hpne": ("hpne", dict(sketch_prec="bf16", qr_prec="fp32", refine_steps=1)),
+    "fp64_pne": ("pne", dict(sketch_prec="fp64", qr_prec="fp64", refine_steps=0)),
+    "fp64_hpne": ("hpne", dict(sketch_prec="fp64", qr_prec="fp64", refine_steps=0)),
+    "srft_fp32_pne": ("pne", dict(sketch_prec="fp32", qr_prec="fp32", refine_steps=0, sketch_kind="srft")),
+    "qr_solver": ("qr", None),
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -49,6 +60,9 @@ def parse():
                     help="skip the m = 1e6 (AUTO) and m = 4e6 (FP8 HPNE) single-problem measurements")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the 512-problem batched measurement (profiling runs); prints its JSON object")
+    ap.add_argument("--only", choices=sorted(ONLY_CASES),
+                    help="time one solver configuration on the single-problem workload and print "
+                         "its JSON object (profiling runs)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run one plain elementwise copy (torch.neg) of 512 MiB first, so that "
                          "hardware byte counters can be scaled against a kernel of known traffic")
@@ -353,6 +367,17 @@ def main():
     print(f"[bench] generating m={M} n={N} kappa={KAPPA:g} rho={RHO:g}", file=sys.stderr, flush=True)
     prob = make_problem(M, N, KAPPA, RHO, seed=1002, device="cuda")
     torch.cuda.synchronize()
+    if args.only:
+        solver, kw = ONLY_CASES[args.only]
+        print(f"[bench] timing {args.only}", file=sys.stderr, flush=True)
+        if solver == "qr":
+            t, e = time_qr_solver(pne, prob, args.steps, args.warmup)
+        else:
+            t, e, _ = time_solver(pne, prob, pne.make_opts(s=S, seed=2, **kw), args.steps, args.warmup,
+                                  hpne=solver == "hpne")
+        print(json.dumps({"case": args.only, "workload": WORKLOAD, "ms": t * 1e3, "rel_err": e,
+                          "steps": args.steps, "warmup": args.warmup}))
+        return
     if args.copy_probe:
         src = torch.zeros(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
         dst = torch.empty_like(src)
