@@ -27,25 +27,7 @@ __device__ __forceinline__ void batched_block_sum(T (&v)[NB], T (*red)[NB], T* b
 {
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     constexpr int LOGNB = (NB == 32) ? 5 : (NB == 16 ? 4 : 3);
-    // transpose-reduce: each halving step keeps half the entries and adds the
-    // partner lane's copy of them.  Both candidate sums are formed explicitly
-    // (selecting between array entries with a lane-dependent condition would
-    // be lowered to an indexed access over the whole array).
-#pragma unroll
-    for (int step = 0; step < LOGNB; ++step) {
-        const int o = 32 >> step;
-        const int half = NB >> (step + 1);
-        const bool hi = (lane & o) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            const T lo_sum = v[i] + __shfl_xor(v[i], o, 64);
-            const T hi_sum = v[i + half] + __shfl_xor(v[i + half], o, 64);
-            v[i] = hi ? hi_sum : lo_sum;
-        }
-    }
-    T s = v[0];
-#pragma unroll
-    for (int o = (32 >> LOGNB); o >= 1; o >>= 1) s += __shfl_xor(s, o, 64);
+    const T s = wave_transpose_total<T, NB>(v);
     const int idx = (lane >> (6 - LOGNB)) & (NB - 1);
     if ((lane & ((64 >> LOGNB) - 1)) == 0) red[wid][idx] = s;
     __syncthreads();
@@ -367,21 +349,7 @@ __device__ __forceinline__ void wave_transpose_sum(T (&v)[NB], T* out)
 {
     constexpr int LOGNB = (NB == 16) ? 4 : 3;
     const int lane = threadIdx.x & 63;
-#pragma unroll
-    for (int step = 0; step < LOGNB; ++step) {
-        const int o = 32 >> step;
-        const int half = NB >> (step + 1);
-        const bool hi = (lane & o) != 0;
-#pragma unroll
-        for (int i = 0; i < half; ++i) {
-            const T lo_sum = v[i] + __shfl_xor(v[i], o, 64);
-            const T hi_sum = v[i + half] + __shfl_xor(v[i + half], o, 64);
-            v[i] = hi ? hi_sum : lo_sum;
-        }
-    }
-    T y = v[0];
-#pragma unroll
-    for (int o = (32 >> LOGNB); o >= 1; o >>= 1) y += __shfl_xor(y, o, 64);
+    const T y = wave_transpose_total<T, NB>(v);
     const int idx = (lane >> (6 - LOGNB)) & (NB - 1);
     if ((lane & ((64 >> LOGNB) - 1)) == 0) out[idx] = y;
 }
