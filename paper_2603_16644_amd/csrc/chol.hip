@@ -27,7 +27,7 @@ struct PotrfStep {
     {
         if (K >= w) return;
         const int lane = threadIdx.x;
-        const T d = __shfl(a[K], K, 64);
+        const T d = lane_value(a[K], K);
         const bool bad = !(d > (T)0) || !isfinite(d);
         if (bad && lane == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + K) + 1;
         const T lkk = bad ? (T)NAN : (T)sqrt(d);
@@ -58,7 +58,7 @@ struct PotrfStep4 {
         const int lane = threadIdx.x & 63, q = threadIdx.x >> 6;
         constexpr int QK = K >> 4, TK = K & 15;
         if (q == QK) {
-            const T d = __shfl(a[TK], K, 64);
+            const T d = lane_value(a[TK], K);
             const bool bad = !(d > (T)0) || !isfinite(d);
             if (bad && lane == 0 && *info == 0) *info = 2000 + (int32_t)(c0 + K) + 1;
             const T lkk = bad ? (T)NAN : (T)sqrt(d);

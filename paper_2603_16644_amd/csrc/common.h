@@ -134,6 +134,44 @@ __device__ __forceinline__ T wave_max(T v)
     return v;
 }
 
+// Value of v in lane l of the wavefront (l uniform; readlane into a scalar
+// register).
+template <typename T>
+__device__ __forceinline__ T lane_value(T v, int l)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t b = __builtin_bit_cast(uint64_t, v);
+        const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+        const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+        return __builtin_bit_cast(T, ((uint64_t)hi << 32) | lo);
+    } else {
+        return __builtin_bit_cast(T, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+    }
+}
+
+// Largest v over the wavefront with its index i (ties: the smaller index);
+// every lane receives the pair.
+template <int O, typename T, typename I>
+__device__ __forceinline__ void argmax_step(T& v, I& i)
+{
+    const T ov = lane_partner<O>(v);
+    const I oi = lane_partner<O>(i);
+    if (ov > v || (ov == v && oi < i)) {
+        v = ov;
+        i = oi;
+    }
+}
+template <typename T, typename I>
+__device__ __forceinline__ void wave_argmax(T& v, I& i)
+{
+    argmax_step<32>(v, i);
+    argmax_step<16>(v, i);
+    argmax_step<8>(v, i);
+    argmax_step<4>(v, i);
+    argmax_step<2>(v, i);
+    argmax_step<1>(v, i);
+}
+
 // Transposing sum of v[0..NB) (NB = 2 .. 32) over the 64 lanes: the total of
 // entry e ends in every lane l with (l >> (6 - log2 NB)) & (NB - 1) == e.
 // Step s halves the entries a lane carries: lanes with bit 32 >> s set keep

@@ -154,12 +154,8 @@ __device__ void Hager::run(const Args& a, int, int)
             if (a > zm) { zm = a; zi = i; }
             ztx += z[i] * x[i];
         }
-        for (int off = 32; off >= 1; off >>= 1) {
-            const float om = __shfl_xor(zm, off, 64);
-            const int64_t oi = __shfl_xor(zi, off, 64);
-            if (om > zm || (om == zm && oi < zi)) { zm = om; zi = oi; }
-            ztx += __shfl_xor(ztx, off, 64);
-        }
+        wave_argmax(zm, zi);
+        ztx = wave_sum(ztx);
         if (lane == 0) { redz[wid] = zm; redi[wid] = zi; redd[wid] = ztx; }
         __syncthreads();
         if (tid == 0) {

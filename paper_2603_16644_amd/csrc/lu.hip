@@ -96,12 +96,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             if (v != v) v = INFINITY;
             if (r >= k && r < h && v > best) { best = v; bidx = r; }
         }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-            const double ov = __shfl_xor(best, off, 64);
-            const int64_t oi = __shfl_xor(bidx, off, 64);
-            if (ov > best || (ov == best && oi < bidx)) { best = ov; bidx = oi; }
-        }
+        wave_argmax(best, bidx);
         if (lane == 0) { sh.wv[B][wid] = best; sh.wi[B][wid] = bidx; }
         __syncthreads();
         double bb = sh.wv[B][0];
