@@ -5,9 +5,12 @@
 //     the panel in registers; per column the pivot is the first row of
 //     largest magnitude (wavefront argmax, ties to the smaller index), the
 //     two rows are exchanged through LDS, the column is scaled and the rest
-//     of the panel gets the rank-1 update; then, in the same kernel, the row
-//     exchanges are applied to the other columns and U12 := L11^{-1} C12
-//     (unit lower forward substitution, one thread per column);
+//     of the panel gets the rank-1 update;
+//   the other columns, one thread per column over many work-groups: the
+//     panel's row exchanges (composed into one permutation of at most 2 PW
+//     rows, so a column's loads are all in flight together instead of one
+//     exchange after another) and, right of the panel, U12 := L11^{-1} C12
+//     (unit lower forward substitution);
 //   C22 -= L21 U12 (MFMA GEMM).
 // A zero or non-finite pivot at global column k sets *info = 3000 + k + 1
 // (first only); that column's elimination is skipped.
@@ -29,17 +32,13 @@ struct LuShared {
     double wv[2][LU_WAVES];
     int64_t wi[2][LU_WAVES];
     int32_t pivl[PW];              // pivot rows of the panel (relative to its first row)
-    double L11[PW][PW + 1];        // unit lower triangle of the factored panel's top rows
 };
 
-// One panel step of the blocked LU in one 512-thread work-group:
-//   1. factor the panel C(c0:n, c0:c0+w) in registers (partial pivoting);
-//   2. apply its row exchanges to every other column;
-//   3. U12 := L11^{-1} C12 for the columns right of the panel (unit lower
-//      forward substitution, L11 from LDS; one thread per column).
-// Steps 2 and 3 take one column per thread at a time; a column's exchanges
-// precede its substitution.  The trailing update C22 -= L21 U12 follows as
-// an MFMA GEMM launch.
+// Panel of the blocked LU in one 512-thread work-group: the panel
+// C(c0:n, c0:c0+w) factored in registers (partial pivoting), written back
+// with its pivot rows.  LuTail then applies the exchanges to the other
+// columns and forms U12; the trailing update C22 -= L21 U12 follows as an
+// MFMA GEMM launch.
 struct LuPanelArgs {
     int64_t n;
     int w;
@@ -63,7 +62,6 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
     double* __restrict__ C = a.C;
     double* __restrict__ P = C + c0 + c0 * ldc;
     __shared__ LuShared<PW> sh;
-    __shared__ double colL[PW * LU_THREADS];   // column segments of the U12 substitution
     const int tid = threadIdx.x;
     const int lane = tid & 63, wid = tid >> 6;
     int32_t* __restrict__ info = a.info;
@@ -156,33 +154,89 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             int col = c + w;
             if (col >= PW) col -= PW;
             if (r < h && col < w) P[r + col * ldc] = x[q][c];
-            if (r < w) sh.L11[r][col] = (col < r) ? x[q][c] : 0.0;
         }
+    }
+    if (tid < w) a.piv[c0 + tid] = (int32_t)(c0 + sh.pivl[tid]);
+}
+
+// The row exchanges of a factored panel (pivots piv[c0 .. c0+w)) applied to
+// every column outside it, and U12 := L11^{-1} C12 right of it; one thread
+// per column.  The exchanges, applied in order k = 0 .. w-1 to the rows
+// c0 + k and piv[c0 + k], move values among at most 2 w rows: one thread
+// composes them into a table (row slot s receives the value that row slot
+// perm[s] held before the panel), then every column loads all the values it
+// needs before it stores any.
+template <int PW>
+struct LuTail {
+    struct Args {
+        int64_t n;
+        int w;
+        double* C;
+        int64_t ldc;
+        const int32_t* piv;
+        int64_t c0;
+    };
+    static constexpr int NTH = 64, WPE = 0;
+    static __device__ void run(const Args& a, int bx, int by);
+};
+template <int PW>
+__device__ void LuTail<PW>::run(const Args& a, int bx, int)
+{
+    __shared__ double L11[PW][PW + 1];
+    __shared__ int32_t srow[2 * PW];   // local row of each slot (slots < w: the panel rows)
+    __shared__ int32_t perm[2 * PW];
+    __shared__ int32_t nslot;
+    const int64_t n = a.n, ldc = a.ldc, c0 = a.c0;
+    const int w = a.w;
+    double* __restrict__ C = a.C;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < PW * PW; e += NTH) {
+        const int i = e % PW, l = e / PW;
+        L11[i][l] = (i < w && l < i) ? C[(c0 + i) + (c0 + l) * ldc] : 0.0;
+    }
+    if (tid == 0) {
+        int ns = w;
+        for (int s = 0; s < w; ++s) { srow[s] = s; perm[s] = s; }
+        for (int k = 0; k < w; ++k) {
+            const int pk = a.piv[c0 + k] - (int32_t)c0;
+            int sp = pk;
+            if (pk >= w) {
+                sp = -1;
+                for (int s = w; s < ns; ++s)
+                    if (srow[s] == pk) sp = s;
+                if (sp < 0) { sp = ns; srow[ns] = pk; perm[ns] = ns; ++ns; }
+            }
+            if (sp != k) { const int t = perm[k]; perm[k] = perm[sp]; perm[sp] = t; }
+        }
+        nslot = ns;
     }
     __syncthreads();
-    if (tid < w) a.piv[c0 + tid] = (int32_t)(c0 + sh.pivl[tid]);
-    for (int64_t j = tid; j < n; j += LU_THREADS) {
-        if (j >= c0 && j < c0 + w) continue;
-        double* col = C + j * ldc + c0;
-        for (int k = 0; k < w; ++k) {
-            const int64_t pk = sh.pivl[k];
-            if (pk != k) { const double t = col[k]; col[k] = col[pk]; col[pk] = t; }
-        }
-        if (j >= c0 + w) {
-            // forward substitution with the unit lower L11 on this thread's
-            // column segment, staged in LDS (element i of thread t at
-            // i * threads + t: conflict-free) with run-time loops, so that no
-            // register array is indexed
-            double* u = colL + tid;
-            for (int i = 0; i < w; ++i) u[i * LU_THREADS] = col[i];
-            for (int i = 1; i < w; ++i) {
-                double v = u[i * LU_THREADS];
-                for (int l = 0; l < i; ++l) v -= sh.L11[i][l] * u[l * LU_THREADS];
-                u[i * LU_THREADS] = v;
-            }
-            for (int i = 0; i < w; ++i) col[i] = u[i * LU_THREADS];
+    // column of this thread: the columns left of the panel, then right of it
+    const int64_t jj = (int64_t)bx * NTH + tid;
+    if (jj >= n - w) return;
+    const int64_t j = jj < c0 ? jj : jj + w;
+    double* __restrict__ col = C + j * ldc + c0;
+    const int ns = nslot;
+    double u[PW], vo[PW];
+#pragma unroll
+    for (int i = 0; i < PW; ++i) u[i] = (i < w) ? col[srow[perm[i]]] : 0.0;
+#pragma unroll
+    for (int s = 0; s < PW; ++s) vo[s] = (w + s < ns) ? col[srow[perm[w + s]]] : 0.0;
+#pragma unroll
+    for (int s = 0; s < PW; ++s)
+        if (w + s < ns) col[srow[w + s]] = vo[s];
+    if (j >= c0 + w) {
+#pragma unroll
+        for (int i = 1; i < PW; ++i) {
+            double v = u[i];
+#pragma unroll
+            for (int l = 0; l < i; ++l) v -= L11[i][l] * u[l];
+            u[i] = v;
         }
     }
+#pragma unroll
+    for (int i = 0; i < PW; ++i)
+        if (i < w) col[i] = u[i];
 }
 
 template <int RPT, int PW>
@@ -191,6 +245,8 @@ static void lu_steps(Exec& ex, int64_t n, double* C, int64_t ldc, int32_t* piv, 
     ex.iter((uint32_t)c0);
     const int w = (int)((n - c0 < PW) ? n - c0 : PW);
     launch<LuPanel<RPT, PW>>(ex, 1, 1, LuPanelArgs{n, w, C, ldc, piv, c0, info});
+    if (n > w)
+        launch<LuTail<PW>>(ex, ceil_div(n - w, 64), 1, typename LuTail<PW>::Args{n, w, C, ldc, piv, c0});
     const int64_t rem = n - c0 - w;
     if (rem <= 0) return;
     GemmArgs g{};

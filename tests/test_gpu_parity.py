@@ -251,6 +251,29 @@ def test_gram_and_factors_elementwise(pne, orc, hpne):
         np.testing.assert_allclose(Lg, Lo, rtol=0, atol=1e-8 * np.abs(Lo).max())
 
 
+@pytest.mark.parametrize("hpne", [False, True])
+@pytest.mark.parametrize("col", [0, 21, 70, 99])
+def test_factor_breakdown_reports_column(pne, orc, hpne, col):
+    """A zero column j of A_p (A with column j zero, R = I) makes C singular
+    at column j: the Cholesky reports 2000 + j + 1 and the LU 3000 + j + 1,
+    as the oracle's factorizations do (columns in the first and in the
+    second, partial, 64-column block, and inside a 16-column step)."""
+    m, n = 1000, 100
+    p = make_problem(m, n, 1e2, 1e-6, seed=1013)
+    A = p.numpy_A().copy(order="F")
+    A[:, col] = 0.0
+    b = p.numpy_b()
+    R = np.eye(n)
+    Co, _ = orc.gram(A, A, b)
+    if hpne:
+        _, _, io = orc.lu(Co)
+    else:
+        _, io = orc.cholesky(Co)
+    assert io == (3000 if hpne else 2000) + col + 1
+    _, _, _, info = pne.pne_gram(dev(A), torch.from_numpy(b).cuda(), dev(R), hpne=hpne, factor=True)
+    assert int(host(info)[0]) == io
+
+
 def test_nan_entry_reports_breakdown(pne):
     """A non-finite entry in A: both solvers report a numerical failure and
     return NaN instead of a wrong x with info 0."""
