@@ -484,8 +484,10 @@ static void lu_solve(int64_t n, const double* LU, int64_t ldlu, const int32_t* p
  * Precision pick (Algorithm 1): FP16 if kappa0 < 4, FP32 if kappa0 <= 8,
  * else FP64 (also when the estimate overflows).  known_kappa > 0 skips the
  * estimate and applies the same thresholds to log10(known_kappa).
- * Parity unpinned for the exact kappa0 value beyond the Hager lower-bound
- * property; the precision picks are pinned by the worked cases of Section 7.4.
+ * Pinned: kappa0 equals (1/2) log10(||G||_1 ||G^{-1}||_1) where Hager's
+ * estimate is exact (diagonal and inverse-positive G), is a lower estimate
+ * within a factor 10 elsewhere, and the precision picks follow the worked
+ * cases of Section 7.4.
  * ---------------------------------------------------------------------- */
 static int pick_precision(float kappa0)
 {

@@ -539,6 +539,34 @@ def test_cond_est_is_a_good_lower_estimate(orc):
         assert math.log10(kappa) <= k0n + 0.05
 
 
+@pytest.mark.parametrize("kind", ["diagonal", "laplacian"])
+def test_cond_est_exact_where_hager_is_exact(orc, kind):
+    """Hager's 1-norm estimate is exact when the inverse has no sign changes
+    it could miss: for a diagonal G it returns max 1 / G_ii, and for an
+    inverse-positive G (the 1D Laplacian tridiag(-1, 2, -1), an M-matrix)
+    the first sign vector is all ones, so the next iterate picks the largest
+    column sum of G^{-1} exactly.  A is built so that G = fl32(A)^T fl32(A)
+    is that matrix (up to the FP32 rounding of A), and kappa0 must equal
+    (1/2) log10(||G||_1 ||G^{-1}||_1) to FP32 accuracy."""
+    n, m = 40, 120
+    if kind == "diagonal":
+        d = np.geomspace(1.0, 1e-3, n)
+        A = np.zeros((m, n))
+        A[:n, :n] = np.diag(d)
+    else:
+        T = 2 * np.eye(n) - np.eye(n, k=1) - np.eye(n, k=-1)
+        A = np.zeros((m, n))
+        A[:n, :n] = np.linalg.cholesky(T).T
+    A32 = A.astype(np.float32).astype(np.float64)
+    G = A32.T @ A32
+    Gi = np.linalg.inv(G)
+    if kind == "laplacian":
+        assert np.all(Gi > 0)
+    exact = 0.5 * math.log10(np.abs(G).sum(0).max() * np.abs(Gi).sum(0).max())
+    k0, _, _ = orc.cond_est(A)
+    assert k0 == pytest.approx(exact, abs=2e-4)
+
+
 def test_known_kappa_thresholds(orc):
     A = np.eye(3)
     assert orc.cond_est(A, known_kappa=1e2)[2] == 3
