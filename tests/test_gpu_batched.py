@@ -74,6 +74,28 @@ def test_batched_deterministic(pne, small_batch):
     assert np.array_equal(x0, host(x))
 
 
+@pytest.mark.parametrize("hpne", [False, True])
+def test_batched_member_independent_of_batch(pne, small_batch, hpne):
+    """A member's x does not depend on the other members: solved inside the
+    full batch and alone (same problem id, so the same sketch), the results
+    are bitwise equal.  Members share every grouped launch, so a race or an
+    indexing slip between members would show up here."""
+    probs, _ = small_batch
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=11, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    info = pne.pne_solve_batched(A, b, x, descs, opts=o, hpne=hpne)
+    assert np.all(host(info) == 0)
+    xb = host(x)
+    for i in (1, 3, 5):
+        p = probs[i]
+        A1, b1, x1, d1 = pack([p])
+        d1[0]["problem_id"] = i
+        info1 = pne.pne_solve_batched(A1, b1, x1, d1, opts=o, hpne=hpne)
+        assert int(host(info1)[0]) == 0
+        d = descs[i]
+        assert np.array_equal(host(x1)[:p.n], xb[d["x_offset"]:d["x_offset"] + p.n]), i
+
+
 def test_batched_auto_mixes_precisions(pne, orc):
     """AUTO picks per member (kappa 1e2 -> half, 3e3 -> single, 1e10 -> double);
     members of different precisions run in the same batched call."""
