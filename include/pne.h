@@ -279,6 +279,8 @@ typedef struct {
     int32_t lower_small_n;
     double ms;        /* median time of one execution with these parameters */
     int32_t stored;   /* 1 if written to the cache file */
+    int32_t persistent; /* 1: the grouped MFMA products run as persistent
+                           launches (work-groups taking tiles from a counter) */
 } pne_tune_result;
 size_t pne_autotune_batched_workspace_size(int64_t batch, const pne_problem_desc* hdesc, const pne_opts* opts,
                                            int hpne);

@@ -56,7 +56,8 @@ class Info(ctypes.Structure):
 
 class TuneResult(ctypes.Structure):
     _fields_ = [("batch_kchunk", ctypes.c_int64), ("shortk_tile", ctypes.c_int32),
-                ("lower_small_n", ctypes.c_int32), ("ms", ctypes.c_double), ("stored", ctypes.c_int32)]
+                ("lower_small_n", ctypes.c_int32), ("ms", ctypes.c_double), ("stored", ctypes.c_int32),
+                ("persistent", ctypes.c_int32)]
 
 
 class ProblemDesc(ctypes.Structure):
@@ -468,4 +469,4 @@ def autotune_batched(A_base, b_base, x_base, descs, opts: Opts | None = None, hp
                                     info.data_ptr(), _stream_ptr(stream), ctypes.byref(res))
     _check("pne_autotune_batched", rc)
     return {"batch_kchunk": res.batch_kchunk, "shortk_tile": res.shortk_tile, "lower_small_n": res.lower_small_n,
-            "ms": res.ms, "stored": bool(res.stored)}
+            "ms": res.ms, "stored": bool(res.stored), "persistent": bool(res.persistent)}

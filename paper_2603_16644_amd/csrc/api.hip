@@ -406,7 +406,7 @@ void batch_layout(int64_t batch, const pne_problem_desc* hd, const pne_opts* o, 
 size_t table_bound(const Recorder& rec)
 {
     size_t b = 256;
-    for (const LaunchRec& r : rec.recs) b += r.args_size + 8 + 4 + 16 + 256;
+    for (const LaunchRec& r : rec.recs) b += r.args_size + 8 + 4 + 16 + 256 + 32;
     return b;
 }
 
@@ -602,6 +602,7 @@ pne_status plan_create(int64_t batch, const pne_problem_desc* hd, const double* 
 // run at creation on the same data).
 pne_status plan_execute(pne_batch_plan_s* plan, hipStream_t st, bool run_ce)
 {
+    TuneScope scope(plan->tune);   // launch forms (persistent or not) chosen with the plan
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
     if (hipStreamIsCapturing(st, &cs) != hipSuccess) return PNE_EHIP;
     const bool marks = cs == hipStreamCaptureStatusNone;
@@ -940,13 +941,15 @@ static std::vector<TuneParams> tune_candidates()
     std::vector<TuneParams> c;
     for (int64_t kc : {4096, 8192, 16384})
         for (int st : {64, 128})
-            for (int ln : {512, 1024}) {
-                TuneParams p;
-                p.batch_kchunk = kc;
-                p.shortk_tile = st;
-                p.lower_small_n = ln;
-                c.push_back(p);
-            }
+            for (int ln : {512, 1024})
+                for (int pe : {0, 1}) {
+                    TuneParams p;
+                    p.batch_kchunk = kc;
+                    p.shortk_tile = st;
+                    p.lower_small_n = ln;
+                    p.persistent = pe;
+                    c.push_back(p);
+                }
     return c;
 }
 
@@ -1017,6 +1020,7 @@ pne_status pne_autotune_batched(int64_t batch, const pne_problem_desc* hdesc, co
         result->batch_kchunk = best.batch_kchunk;
         result->shortk_tile = best.shortk_tile;
         result->lower_small_n = best.lower_small_n;
+        result->persistent = best.persistent;
         result->ms = best_ms;
         result->stored = stored ? 1 : 0;
     }

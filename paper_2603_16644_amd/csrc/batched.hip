@@ -20,6 +20,7 @@
 #include "kernels.h"
 #include "launch.h"
 #include "profile.h"
+#include "tune.h"
 
 namespace pne {
 
@@ -67,7 +68,8 @@ int build_groups(const Recorder& rec, GroupSeq* out)
         const int count = (int)(j - i);
         const size_t off = (blob.size() + 255) & ~(size_t)255;
         const size_t aoff = (size_t)group_args_offset(count);
-        blob.resize(off + aoff + (size_t)count * r0.args_size);
+        // arguments, then the two work counters of a persistent launch (zero)
+        blob.resize(off + (size_t)group_counter_offset(count, r0.args_size) + GROUP_COUNTER_BYTES, 0);
         int32_t* start = (int32_t*)(blob.data() + off);
         int32_t* gx = start + count + 1;
         int64_t total = 0;
@@ -89,9 +91,10 @@ int build_groups(const Recorder& rec, GroupSeq* out)
 
 void enqueue_groups(const std::vector<LaunchGroup>& groups, const char* dtables, hipStream_t st, bool marks)
 {
+    const int persistent = tune_params().persistent;
     for (size_t g = 0; g < groups.size(); ++g) {
         const LaunchGroup& G = groups[g];
-        G.fn(dtables + G.off, G.count, G.total, st);
+        G.fn(dtables + G.off, G.count, G.total, st, persistent);
         if (!marks) continue;
         const bool last = g + 1 == groups.size();
         if (last || stage_phase(groups[g + 1].stage) != stage_phase(G.stage)) prof_mark(stage_phase(G.stage), st);

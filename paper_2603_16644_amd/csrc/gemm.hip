@@ -42,6 +42,7 @@ template <typename TA, typename TB, typename TC, int BM, int BN, bool PARTIAL>
 struct GemmCm {
     typedef GemmArgs Args;
     static constexpr int NTH = 256, WPE = BM == 64 ? 3 : 2;
+    static constexpr bool PERSIST = true;   // no early return: may run as a persistent grouped launch
     static __device__ void run(const GemmArgs& g, int bx, int by);
 };
 

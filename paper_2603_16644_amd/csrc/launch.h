@@ -23,6 +23,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <type_traits>
 #include <vector>
 
 #include "common.h"
@@ -35,14 +36,21 @@ __host__ __device__ inline int64_t group_args_offset(int count)
     return ((int64_t)(2 * count + 1) * 4 + 15) & ~(int64_t)15;
 }
 
-// Locate this work-group's member in a group table and run its share.
+// byte offset of the two work counters after the arguments (next work
+// item, work-groups finished; used by persistent launches, zero otherwise)
+__host__ __device__ inline int64_t group_counter_offset(int count, int64_t args_size)
+{
+    return (group_args_offset(count) + (int64_t)count * args_size + 15) & ~(int64_t)15;
+}
+constexpr int64_t GROUP_COUNTER_BYTES = 16;
+
+// Locate work-group b's member in a group table and run its share.
 template <class K>
-__device__ __forceinline__ void grouped_body(const char* __restrict__ table, int count)
+__device__ __forceinline__ void grouped_item(const char* __restrict__ table, int count, int32_t b)
 {
     const int32_t* start = (const int32_t*)table;
     const int32_t* gx = start + count + 1;
     const typename K::Args* args = (const typename K::Args*)(table + group_args_offset(count));
-    const int32_t b = (int32_t)blockIdx.x;
     int lo = 0, hi = count - 1;
     while (lo < hi) {  // last member whose first work-group is <= b
         const int mid = (lo + hi + 1) >> 1;
@@ -53,6 +61,41 @@ __device__ __forceinline__ void grouped_body(const char* __restrict__ table, int
     const int32_t w = gx[lo];
     const typename K::Args a = args[lo];
     K::run(a, local % w, local / w);
+}
+template <class K>
+__device__ __forceinline__ void grouped_body(const char* __restrict__ table, int count)
+{
+    grouped_item<K>(table, count, (int32_t)blockIdx.x);
+}
+
+// Persistent form of a grouped launch: as many work-groups as fit on the
+// machine at once, each taking work items (the work-groups of the ordinary
+// launch, in order) from the table's counter until they run out.  The last
+// work-group to finish puts the counters back to zero, so the table serves
+// the next launch, or the next replay of a captured graph, as it is.  Every
+// item computes what the ordinary launch's work-group does, in the same
+// order, so results are bitwise the same.  For kernels without an early
+// return (every thread reaches every barrier of K::run).
+template <class K>
+__device__ __forceinline__ void persistent_body(const char* __restrict__ table, int count, int32_t total)
+{
+    int32_t* ctr = (int32_t*)(const_cast<char*>(table) + group_counter_offset(count, sizeof(typename K::Args)));
+    __shared__ int32_t item;
+    for (;;) {
+        if (threadIdx.x == 0) item = __hip_atomic_fetch_add(&ctr[0], 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int32_t it = item;
+        __syncthreads();
+        if (it >= total) break;
+        grouped_item<K>(table, count, it);
+    }
+    if (threadIdx.x == 0) {
+        const int32_t done = __hip_atomic_fetch_add(&ctr[1], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (done == (int32_t)gridDim.x - 1) {
+            __hip_atomic_store(&ctr[0], 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&ctr[1], 0, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // Kernels with K::WPE > 0 carry an occupancy target of WPE waves per SIMD
@@ -80,11 +123,45 @@ void grouped_kernel_wpe(const char* __restrict__ table, int count)
     grouped_body<K>(table, count);
 }
 
-typedef void (*GroupLaunchFn)(const char* dtable, int count, int64_t total_wgs, hipStream_t st);
+template <class K>
+__global__ __launch_bounds__(K::NTH) __attribute__((amdgpu_waves_per_eu(K::WPE, K::WPE)))
+void persistent_kernel_wpe(const char* __restrict__ table, int count, int32_t total)
+{
+    persistent_body<K>(table, count, total);
+}
+
+// Kernels that may run persistent declare `static constexpr bool PERSIST`.
+template <class K, class = void>
+struct can_persist : std::false_type {};
+template <class K>
+struct can_persist<K, std::void_t<decltype(K::PERSIST)>> : std::integral_constant<bool, K::PERSIST> {};
+
+// Work-groups of K that fit on the device at once (queried once per kernel).
+template <class K>
+int64_t persistent_grid()
+{
+    static int64_t g = [] {
+        int dev = 0, cus = 0, per_cu = 0;
+        (void)hipGetDevice(&dev);
+        (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, persistent_kernel_wpe<K>, K::NTH, 0);
+        return (int64_t)(cus > 0 ? cus : 1) * (per_cu > 0 ? per_cu : 1);
+    }();
+    return g;
+}
+
+typedef void (*GroupLaunchFn)(const char* dtable, int count, int64_t total_wgs, hipStream_t st, int persistent);
 
 template <class K>
-void group_launch(const char* dtable, int count, int64_t total_wgs, hipStream_t st)
+void group_launch(const char* dtable, int count, int64_t total_wgs, hipStream_t st, int persistent)
 {
+    if constexpr (K::WPE > 0 && can_persist<K>::value) {
+        const int64_t g = persistent ? persistent_grid<K>() : 0;
+        if (g > 0 && g < total_wgs) {
+            persistent_kernel_wpe<K><<<dim3((uint32_t)g), K::NTH, 0, st>>>(dtable, count, (int32_t)total_wgs);
+            return;
+        }
+    }
     if constexpr (K::WPE > 0) grouped_kernel_wpe<K><<<dim3((uint32_t)total_wgs), K::NTH, 0, st>>>(dtable, count);
     else grouped_kernel<K><<<dim3((uint32_t)total_wgs), K::NTH, 0, st>>>(dtable, count);
 }

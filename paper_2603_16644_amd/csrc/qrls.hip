@@ -138,7 +138,7 @@ int record_level(Recorder& rec, const QrlsPlan& p, int level, int64_t m, int64_t
 size_t table_bytes(const Recorder& rec)
 {
     size_t t = 256;
-    for (const LaunchRec& r : rec.recs) t += r.args_size + 8 + 4 + 16 + 256;
+    for (const LaunchRec& r : rec.recs) t += r.args_size + 8 + 4 + 16 + 256 + 32;
     return t;
 }
 

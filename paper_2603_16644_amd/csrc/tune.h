@@ -17,6 +17,7 @@ struct TuneParams {
     int64_t batch_kchunk = 8192;   // rows per split-K chunk of the long products of a batch
     int shortk_tile = 64;          // output tile (64 or 128) of products with K < 4096
     int lower_small_n = 512;       // lower-triangle long-K products of order <= this use 64 x 64 tiles
+    int persistent = 0;            // 1: grouped MFMA products as persistent launches (launch.h)
 };
 
 // Parameters in force on this thread.

@@ -1,7 +1,7 @@
 // Tunable launch parameters: per-thread scope and the JSON cache file.
 //
 // Cache format ($PNE_TUNE_CACHE): one JSON object whose members are
-//   "<key>": {"batch_kchunk": K, "shortk_tile": T, "lower_small_n": L, "ms": t}
+//   "<key>": {"batch_kchunk": K, "shortk_tile": T, "lower_small_n": L, "persistent": P, "ms": t}
 // written by this file only; the reader accepts exactly that shape (any
 // whitespace).  Reads go through an in-memory copy refreshed when the file's
 // modification time or size changes.
@@ -89,6 +89,7 @@ bool parse_cache(const char* s, std::map<std::string, Entry>* out)
             if (f == "batch_kchunk") e.p.batch_kchunk = (int64_t)v;
             else if (f == "shortk_tile") e.p.shortk_tile = (int)v;
             else if (f == "lower_small_n") e.p.lower_small_n = (int)v;
+            else if (f == "persistent") e.p.persistent = (int)v;
             else if (f == "ms") e.ms = v;
             skip_ws(s);
             if (*s == ',') { ++s; continue; }
@@ -105,7 +106,7 @@ bool parse_cache(const char* s, std::map<std::string, Entry>* out)
 bool valid(const TuneParams& p)
 {
     return p.batch_kchunk >= 256 && p.batch_kchunk <= (1 << 22) && (p.shortk_tile == 64 || p.shortk_tile == 128) &&
-           p.lower_small_n >= 0 && p.lower_small_n <= 4096;
+           p.lower_small_n >= 0 && p.lower_small_n <= 4096 && (p.persistent == 0 || p.persistent == 1);
 }
 
 // Reload the in-memory copy if the file changed (g_mu held).
@@ -179,9 +180,9 @@ bool tune_store(const std::string& key, const TuneParams& p, double ms)
     fprintf(f, "{\n");
     size_t i = 0;
     for (const auto& kv : g_cache) {
-        fprintf(f, "  \"%s\": {\"batch_kchunk\": %lld, \"shortk_tile\": %d, \"lower_small_n\": %d, \"ms\": %.4f}%s\n",
+        fprintf(f, "  \"%s\": {\"batch_kchunk\": %lld, \"shortk_tile\": %d, \"lower_small_n\": %d, \"persistent\": %d, \"ms\": %.4f}%s\n",
                 kv.first.c_str(), (long long)kv.second.p.batch_kchunk, kv.second.p.shortk_tile,
-                kv.second.p.lower_small_n, kv.second.ms, ++i < g_cache.size() ? "," : "");
+                kv.second.p.lower_small_n, kv.second.p.persistent, kv.second.ms, ++i < g_cache.size() ? "," : "");
     }
     fprintf(f, "}\n");
     const bool ok = fclose(f) == 0 && rename(tmp.c_str(), path) == 0;

@@ -175,6 +175,41 @@ def test_plan_graph_replays_match_uncaptured(pne, small_batch, auto):
     plan.close()
 
 
+def test_persistent_launches_match_ordinary(pne, small_batch, tmp_path, monkeypatch):
+    """The grouped MFMA products run as persistent launches (as many
+    work-groups as fit, taking their tiles from a counter in the group
+    table) give bitwise the results of the ordinary grouped launches, in a
+    one-shot call and in a plan replayed three times from a hipGraph (the
+    counters must be back at zero after every launch)."""
+    import json
+    probs, _ = small_batch
+    cache = tmp_path / "tune.json"
+    monkeypatch.setenv("PNE_TUNE_CACHE", str(cache))
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=13, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    pne.autotune_batched(A, b, x, descs, opts=o)
+    (key, entry), = json.loads(cache.read_text()).items()
+    outs = {}
+    for pe in (0, 1):
+        # a different file size, so that the library reads the file again
+        cache.write_text(json.dumps({key: dict(entry, persistent=pe)}, indent=1 + 3 * pe))
+        x.zero_()
+        info = pne.pne_solve_batched(A, b, x, descs, opts=o)
+        assert np.all(host(info) == 0)
+        outs[pe] = host(x).copy()
+        st = torch.cuda.Stream()
+        with torch.cuda.stream(st):
+            plan = pne.BatchPlan(A, b, x, descs, opts=o, stream=st)
+            for k in range(3):
+                x.fill_(float("nan"))
+                info = plan.execute_graph(st)
+                st.synchronize()
+                assert np.all(host(info) == 0)
+                assert np.array_equal(host(x), outs[pe]), (pe, k)
+        plan.close()
+    assert np.array_equal(outs[0], outs[1])
+
+
 def test_autotuner_stores_and_reuses_parameters(pne, small_batch, tmp_path, monkeypatch):
     """The autotuner times its candidates on the batch, stores the fastest in
     $PNE_TUNE_CACHE; later batched calls of the same workload read it back
@@ -189,10 +224,12 @@ def test_autotuner_stores_and_reuses_parameters(pne, small_batch, tmp_path, monk
     res = pne.autotune_batched(A, b, x, descs, opts=o)
     assert res["stored"] and res["ms"] > 0
     assert res["batch_kchunk"] in (4096, 8192, 16384) and res["shortk_tile"] in (64, 128)
+    assert res["persistent"] in (False, True)
     data = json.loads(cache.read_text())
     assert len(data) == 1
     (key, entry), = data.items()
     assert key.startswith("batched/pne/sk4/qr2/") and entry["batch_kchunk"] == res["batch_kchunk"]
+    assert entry["persistent"] == int(res["persistent"])
     x.zero_()
     info = pne.pne_solve_batched(A, b, x, descs, opts=o)
     assert np.all(host(info) == 0)
