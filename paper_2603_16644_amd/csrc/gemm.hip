@@ -6,7 +6,9 @@
 // C = alpha op(A) op(B) + beta Cin on 128 x BN output tiles (BN = 64 or 128),
 // 256 threads = 2 x 2 waves, MFMA 16x16x4 (v_mfma_f64_16x16x4f64 or
 // v_mfma_f32_16x16x4f32), K staged through LDS 16 deep with the next K tile
-// prefetched into registers.  The MFMA operands are fed swapped (op(B)^T as
+// prefetched into registers, or, for the FP64 Gram products (both operands
+// stored with K contiguous), copied from memory straight into LDS.  The MFMA
+// operands are fed swapped (op(B)^T as
 // the instruction's A, op(A)^T as its B) so that lane l owns output rows
 // i = l % 16: consecutive lanes write consecutive addresses of the
 // column-major result.  Output layout of the 16x16 result in lane l,
@@ -57,8 +59,8 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     constexpr int BPT = BN / 16;               // B elements per thread per K tile
     constexpr int TPR = 256 / BM;              // threads per row of op(A) (transposed load)
     // two LDS buffers: the tile in use and the next one
-    __shared__ TC As[2][G_BK * LDA_S];
-    __shared__ TC Bs[2][G_BK * LDB_S];
+    __shared__ __attribute__((aligned(16))) TC As[2][G_BK * LDA_S];
+    __shared__ __attribute__((aligned(16))) TC Bs[2][G_BK * LDB_S];
     __shared__ TC bsh[2][G_BK];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -218,6 +220,109 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
         }
     }
 
+    // Direct-to-LDS path (FP64, 128 x 128 tiles, op(A) = A^T and op(B) = B:
+    // both operands stored with K contiguous, as in the Gram products).  The
+    // K tiles go from memory straight into LDS (global_load_lds_dwordx4, no
+    // register staging and no LDS stores), two buffers, one barrier per tile.
+    // LDS tile of an operand: 128 columns (rows of C) x 16 K values, 128 B
+    // per column; 16-byte slot s of column c holds the K pair
+    // s ^ ((c >> 1) & 7), so that the 16 lanes of a 16-byte read (16
+    // consecutive columns, one K pair) hit 16 different bank groups.  The
+    // MFMA of step s takes K = 4 (l / 16) + s in lane l (any assignment of
+    // the 16 K values to (step, lane group) gives the same sum as long as
+    // both operands use it), so each lane reads its four K values of a column
+    // as two 16-byte loads.
+    bool dma = false;
+    if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128)
+        dma = g.transA && !g.transB && vecA && vecB && ((kend - kbeg) % G_BK) == 0 && kend - kbeg >= 2 * G_BK &&
+              (kbeg & 1) == 0;
+    if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128) {
+      if (dma) {
+        typedef __attribute__((address_space(3))) void* lds_ptr;
+        // per-lane source offsets of the four 1 KB chunks this wavefront
+        // moves per operand (chunk I = columns 8 I .. 8 I + 7; columns past
+        // the matrix read its last column, whose results are never stored)
+        int64_t offa[4], offb[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int c = 8 * (w * 4 + j) + (lane >> 3);
+            const int kp = (lane & 7) ^ ((c >> 1) & 7);
+            const int64_t ca = (i0 + c < g.M) ? i0 + c : g.M - 1;
+            const int64_t cb = (j0 + c < g.N) ? j0 + c : g.N - 1;
+            offa[j] = ca * g.lda + 2 * kp;
+            offb[j] = cb * g.ldb + 2 * kp;
+        }
+        auto dma_tile = [&](int64_t k0, int b) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int I = w * 4 + j;
+                __builtin_amdgcn_global_load_lds((const void*)(A + k0 + offa[j]), (lds_ptr)(As[b] + I * 128), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(B + k0 + offb[j]), (lds_ptr)(Bs[b] + I * 128), 16, 0, 0);
+            }
+        };
+        const int sw = (r16 >> 1) & 7;   // swizzle of every column this lane reads
+        double2 xa[TM][2], xb[TN][2];
+        auto read_ops = [&](int b) {
+            const TC* as = As[b];
+            const TC* bs = Bs[b];
+#pragma unroll
+            for (int t = 0; t < TM; ++t) {
+                const int c = wm * 64 + t * 16 + r16;
+                xa[t][0] = *(const double2*)(as + c * 16 + ((2 * g4) ^ sw) * 2);
+                xa[t][1] = *(const double2*)(as + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
+            }
+#pragma unroll
+            for (int t = 0; t < TN; ++t) {
+                const int c = wn * 64 + t * 16 + r16;
+                xb[t][0] = *(const double2*)(bs + c * 16 + ((2 * g4) ^ sw) * 2);
+                xb[t][1] = *(const double2*)(bs + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
+            }
+        };
+        auto mfma_ops = [&]() {
+#pragma unroll
+            for (int s = 0; s < 4; ++s)
+#pragma unroll
+                for (int a = 0; a < TM; ++a)
+#pragma unroll
+                    for (int b2 = 0; b2 < TN; ++b2) {
+                        const double fa = (s & 1) ? xa[a][s >> 1].y : xa[a][s >> 1].x;
+                        const double fb = (s & 1) ? xb[b2][s >> 1].y : xb[b2][s >> 1].x;
+                        acc[a][b2] = mfma_cm<TC>(fb, fa, acc[a][b2]);
+                    }
+        };
+        // op(A) b by the folding work-groups: thread tid < 128 sums column tid
+        // of the tile in K order
+        auto fold_dma = [&](int b, int64_t k0) {
+            if (fold && tid < BM) {
+                const TC* as = As[b] + tid * 16;
+                const int sv = (tid >> 1) & 7;
+#pragma unroll
+                for (int kp = 0; kp < 8; ++kp) {
+                    const double2 v = *(const double2*)(as + (kp ^ sv) * 2);
+                    cpart += v.x * (TC)bv[k0 + 2 * kp];
+                    cpart += v.y * (TC)bv[k0 + 2 * kp + 1];
+                }
+            }
+        };
+        // Per tile: wait for its copies, barrier, read the MFMA operands and
+        // the fold's column out of LDS, then start the copies of the next
+        // tile into the other buffer and run the MFMAs while they fly (the
+        // copies come after every LDS read of the step, so no wait for them
+        // is needed before those reads).
+        const int64_t nk = (kend - kbeg) / G_BK;
+        dma_tile(kbeg, 0);
+        for (int64_t t = 0; t < nk; ++t) {
+            const int b = (int)(t & 1);
+            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's copies of tile t are in LDS
+            __syncthreads();                      // everyone's; and buffer b ^ 1 is no longer read
+            if (!idle) read_ops(b);
+            fold_dma(b, kbeg + t * G_BK);
+            if (t + 1 < nk) dma_tile(kbeg + (t + 1) * G_BK, b ^ 1);
+            if (!idle) mfma_ops();
+        }
+      }
+    }
+
     // Fast path (FP64 operands, full tile off the diagonal of a lower-
     // triangle product, 16-byte aligned vector loads, a K range of at least
     // two whole tiles): no bounds checks, and every step of the steady state
@@ -226,7 +331,8 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     // that the scheduler can interleave them and the MFMA pipe keeps running
     // while they issue.  64 x 64 tiles only: on the products of A R^-1 it
     // raised the MFMA busy share from 57 % to 64 %, while the 128 x 128
-    // tiles of the Gram product ran slower with it (61 % against 64 %).
+    // tiles of the Gram product ran slower with it (61 % against 64 %; they
+    // take the direct-to-LDS path above).
     bool fast = false;
     if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 64)
         fast = vecA && vecB && i0 + BM <= g.M && j0 + BN <= g.N && ((kend - kbeg) % G_BK) == 0 &&
@@ -324,6 +430,7 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     // Pipeline: tile t is in LDS buffer t % 2 while tile t + 1 is being
     // loaded into registers; one barrier per tile.
     int buf = 0;
+    if (dma) fast = true;   // (its K loop has run)
     if (!fast && kbeg < kend) {
         gload(kbeg);
         sstore(0);
