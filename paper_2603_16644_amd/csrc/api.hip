@@ -77,8 +77,9 @@ size_t scratch_bytes(const Problem& p, int sk, int qr)
                                   : sketch_workspace_bytes(p.m, p.n, p.s, sk, p.br, p.kchunk_fixed);
     size_t q = qr_workspace_bytes(p.s, p.n, qr);
     if (q > b) b = q;
-    int64_t splits, kc;
-    plan_splitk(p.m, gemm_tiles(p.n, p.n, p.m, !p.hpne), &splits, &kc, p.kchunk_fixed);
+    int64_t splits, kc, sd, kcd;
+    plan_splitk_gram(p.m, p.n, !p.hpne, p.kchunk_fixed, &splits, &kc, &sd, &kcd);
+    if (sd > splits) splits = sd;
     size_t g = ((size_t)splits * p.n * p.n + (size_t)splits * p.n) * sizeof(double) + 512;
     if (g > b) b = g;
     return b;
@@ -250,9 +251,8 @@ void run_gram(Exec& ex, const Problem& p, const double* dA, const double* db, co
     trsm_right_upper(ex, m, n, dA, lda, b.R, n, b.Ap, m);
     mark(ex, PH_TRSM);
     ex.stage(ST_GRAM);
-    int64_t splits, kc;
-    const int64_t gtiles = gemm_tiles(n, n, m, !hpne);
-    plan_splitk(m, gtiles, &splits, &kc, ex.kchunk_fixed);
+    int64_t splits, kc, sd, kcd;
+    plan_splitk_gram(m, n, !hpne, ex.kchunk_fixed, &splits, &kc, &sd, &kcd);
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;
     g.A = b.Ap; g.lda = m; g.transA = 1;
@@ -261,8 +261,9 @@ void run_gram(Exec& ex, const Problem& p, const double* dA, const double* db, co
     g.C = b.C; g.ldc = n;
     g.lower = !hpne;
     g.splits = splits; g.kchunk = kc;
+    g.splits_diag = sd; g.kchunk_diag = kcd;
     g.P = b.scratch;
-    g.Pc = (double*)b.scratch + (size_t)splits * n * n;
+    g.Pc = (double*)b.scratch + (size_t)(sd > splits ? sd : splits) * n * n;
     g.bvec = db; g.cvec = b.c;
     gemm_f64_partials(ex, g);
     mark(ex, PH_GRAM_GEMM);

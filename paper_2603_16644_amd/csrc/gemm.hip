@@ -81,11 +81,29 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
         bx = (int)(v % gxw);
         by = (int)(v / gxw);
     }
-    if (g.lower) lower_tile(bx, ti, tj);
+    // K chunk of the work-group: by, or, with a separate split of the
+    // diagonal tiles (one-dimensional grid), from the work-group index: the
+    // first tiles_m * splits_diag work-groups take the diagonal tiles, the
+    // rest the tiles below the diagonal
+    int64_t split = by, kc = g.kchunk;
+    if (PARTIAL && g.lower && g.splits_diag > 0) {
+        const int64_t v = bx + (int64_t)by * gridDim.x;
+        const int64_t nd = tiles_m * g.splits_diag;
+        if (v < nd) {
+            ti = tj = v % tiles_m;
+            split = v / tiles_m;
+            kc = g.kchunk_diag;
+        } else {
+            const int64_t u = v - nd, nf = tiles_m * (tiles_m - 1) / 2;
+            lower_tile(u % nf, ti, tj);
+            ++ti;
+            split = u / nf;
+        }
+    } else if (g.lower) lower_tile(bx, ti, tj);
     else { ti = bx % tiles_m; tj = bx / tiles_m; }
     const int64_t i0 = ti * BM, j0 = tj * BN;
-    const int64_t kbeg = PARTIAL ? (int64_t)by * g.kchunk : 0;
-    int64_t kend = PARTIAL ? kbeg + g.kchunk : g.K;
+    const int64_t kbeg = PARTIAL ? split * kc : 0;
+    int64_t kend = PARTIAL ? kbeg + kc : g.K;
     if (kend > g.K) kend = g.K;
 
     const TA* __restrict__ A = (const TA*)g.A;
@@ -109,6 +127,9 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
 #pragma unroll
         for (int b = 0; b < TN; ++b) acc[a][b] = (VC){0, 0, 0, 0};
     TC cpart = 0;
+    // quadrant and 16-column blocks of C that the wavefront writes, and the
+    // thread's column of the op(A) b fold
+    int ewm = wm, ewn = wn, bmask = (1 << TN) - 1, fc = tid;
 
     TC ra[APT], rb[BPT], rbv = 0;
     // Load the K tile starting at k0 into registers (zero outside the matrix).
@@ -235,31 +256,58 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     bool dma = false;
     if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128)
         dma = g.transA && !g.transB && vecA && vecB && ((kend - kbeg) % G_BK) == 0 && kend - kbeg >= 2 * G_BK &&
-              (kbeg & 1) == 0;
+              (kbeg & 1) == 0 && g.lda < (INT64_C(1) << 22) && g.ldb < (INT64_C(1) << 22);
     if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128) {
       if (dma) {
         typedef __attribute__((address_space(3))) void* lds_ptr;
         // per-lane source offsets of the four 1 KB chunks this wavefront
         // moves per operand (chunk I = columns 8 I .. 8 I + 7; columns past
         // the matrix read its last column, whose results are never stored)
-        int64_t offa[4], offb[4];
+        // (byte offsets from the tile's first column, 32-bit: the launch
+        // requires 128 columns of either operand to span less than 4 GiB)
+        uint32_t offa[4], offb[4];
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int c = 8 * (w * 4 + j) + (lane >> 3);
             const int kp = (lane & 7) ^ ((c >> 1) & 7);
-            const int64_t ca = (i0 + c < g.M) ? i0 + c : g.M - 1;
-            const int64_t cb = (j0 + c < g.N) ? j0 + c : g.N - 1;
-            offa[j] = ca * g.lda + 2 * kp;
-            offb[j] = cb * g.ldb + 2 * kp;
+            const int64_t ca = (i0 + c < g.M) ? c : g.M - 1 - i0;
+            const int64_t cb = (j0 + c < g.N) ? c : g.N - 1 - j0;
+            offa[j] = (uint32_t)((ca * g.lda + 2 * kp) * 8);
+            offb[j] = (uint32_t)((cb * g.ldb + 2 * kp) * 8);
         }
+        const char* abase = (const char*)(A + i0 * g.lda);
+        const char* bbase = (const char*)(B + j0 * g.ldb);
         auto dma_tile = [&](int64_t k0, int b) {
+            const char* pa = abase + k0 * 8;
+            const char* pb = bbase + k0 * 8;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int I = w * 4 + j;
-                __builtin_amdgcn_global_load_lds((const void*)(A + k0 + offa[j]), (lds_ptr)(As[b] + I * 128), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((const void*)(B + k0 + offb[j]), (lds_ptr)(Bs[b] + I * 128), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(pa + offa[j]), (lds_ptr)(As[b] + I * 128), 16, 0, 0);
+                __builtin_amdgcn_global_load_lds((const void*)(pb + offb[j]), (lds_ptr)(Bs[b] + I * 128), 16, 0, 0);
             }
         };
+        // Diagonal tiles of a lower-triangle product: the two wavefronts on
+        // the diagonal take the lower triangles of their quadrants (10 of 16
+        // MFMA blocks), and the other two split the quadrant below the
+        // diagonal by 32-column halves (8 blocks each), so that no SIMD
+        // carries more than 10 blocks; nobody computes the quadrant above
+        // the diagonal.  role: 0 = whole quadrant, 1 = lower triangle,
+        // 2 / 3 = left / right half.  The fold runs on the two half
+        // wavefronts.
+        int role = 0;
+        if (g.lower && ti == tj) {
+            if (wm == wn) role = 1;
+            else {
+                ewm = 1;
+                ewn = 0;
+                role = (w == 1) ? 2 : 3;
+                bmask = (role == 2) ? 0x3 : 0xC;
+            }
+            fc = tid - 64;
+        }
+        role = __builtin_amdgcn_readfirstlane(role);   // (uniform per wavefront)
+        const bool fthr = fold && fc >= 0 && fc < BM;
         const int sw = (r16 >> 1) & 7;   // swizzle of every column this lane reads
         double2 xa[TM][2], xb[TN][2];
         auto read_ops = [&](int b) {
@@ -267,35 +315,39 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
             const TC* bs = Bs[b];
 #pragma unroll
             for (int t = 0; t < TM; ++t) {
-                const int c = wm * 64 + t * 16 + r16;
+                const int c = ewm * 64 + t * 16 + r16;
                 xa[t][0] = *(const double2*)(as + c * 16 + ((2 * g4) ^ sw) * 2);
                 xa[t][1] = *(const double2*)(as + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
             }
 #pragma unroll
             for (int t = 0; t < TN; ++t) {
-                const int c = wn * 64 + t * 16 + r16;
+                const int c = ewn * 64 + t * 16 + r16;
                 xb[t][0] = *(const double2*)(bs + c * 16 + ((2 * g4) ^ sw) * 2);
                 xb[t][1] = *(const double2*)(bs + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
             }
         };
-        auto mfma_ops = [&]() {
+        auto mfma_ops = [&](auto rl) {
+            constexpr int RL = decltype(rl)::value;
 #pragma unroll
             for (int s = 0; s < 4; ++s)
 #pragma unroll
                 for (int a = 0; a < TM; ++a)
 #pragma unroll
                     for (int b2 = 0; b2 < TN; ++b2) {
+                        if (RL == 1 && a < b2) continue;
+                        if (RL == 2 && b2 >= TN / 2) continue;
+                        if (RL == 3 && b2 < TN / 2) continue;
                         const double fa = (s & 1) ? xa[a][s >> 1].y : xa[a][s >> 1].x;
                         const double fb = (s & 1) ? xb[b2][s >> 1].y : xb[b2][s >> 1].x;
                         acc[a][b2] = mfma_cm<TC>(fb, fa, acc[a][b2]);
                     }
         };
-        // op(A) b by the folding work-groups: thread tid < 128 sums column tid
-        // of the tile in K order
+        // op(A) b by the folding work-groups: thread fthr sums column fc of
+        // the tile in K order
         auto fold_dma = [&](int b, int64_t k0) {
-            if (fold && tid < BM) {
-                const TC* as = As[b] + tid * 16;
-                const int sv = (tid >> 1) & 7;
+            if (fthr) {
+                const TC* as = As[b] + fc * 16;
+                const int sv = (fc >> 1) & 7;
 #pragma unroll
                 for (int kp = 0; kp < 8; ++kp) {
                     const double2 v = *(const double2*)(as + (kp ^ sv) * 2);
@@ -310,15 +362,24 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
         // copies come after every LDS read of the step, so no wait for them
         // is needed before those reads).
         const int64_t nk = (kend - kbeg) / G_BK;
-        dma_tile(kbeg, 0);
-        for (int64_t t = 0; t < nk; ++t) {
-            const int b = (int)(t & 1);
-            __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's copies of tile t are in LDS
-            __syncthreads();                      // everyone's; and buffer b ^ 1 is no longer read
-            if (!idle) read_ops(b);
-            fold_dma(b, kbeg + t * G_BK);
-            if (t + 1 < nk) dma_tile(kbeg + (t + 1) * G_BK, b ^ 1);
-            if (!idle) mfma_ops();
+        // one copy of the K loop per role
+        auto kloop = [&](auto rl) {
+            dma_tile(kbeg, 0);
+            for (int64_t t = 0; t < nk; ++t) {
+                const int b = (int)(t & 1);
+                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's copies of tile t are in LDS
+                __syncthreads();                      // everyone's; and buffer b ^ 1 is no longer read
+                read_ops(b);
+                fold_dma(b, kbeg + t * G_BK);
+                if (t + 1 < nk) dma_tile(kbeg + (t + 1) * G_BK, b ^ 1);
+                mfma_ops(rl);
+            }
+        };
+        switch (role) {
+        case 0: kloop(std::integral_constant<int, 0>{}); break;
+        case 1: kloop(std::integral_constant<int, 1>{}); break;
+        case 2: kloop(std::integral_constant<int, 2>{}); break;
+        default: kloop(std::integral_constant<int, 3>{}); break;
         }
       }
     }
@@ -471,37 +532,37 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     // the loads are not serialised behind stores one by one.
     TC* C = (TC*)g.C;
     const TC* Cin = (const TC*)g.Cin;
-    TC* P = PARTIAL ? (TC*)g.P + (int64_t)by * g.M * g.N : nullptr;
+    TC* P = PARTIAL ? (TC*)g.P + split * g.M * g.N : nullptr;
     const TC* src = PARTIAL ? (g.accumulate_partials ? P : nullptr) : Cin;
     const int64_t lds_ = PARTIAL ? g.M : g.ldcin;
 #pragma unroll
     for (int a = 0; a < TM; ++a) {
-        const int64_t i = i0 + wm * (BM / 2) + a * 16 + r16;
+        const int64_t i = i0 + ewm * (BM / 2) + a * 16 + r16;
         TC prev[TN][4];
 #pragma unroll
         for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t j = j0 + wn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
+                const int64_t j = j0 + ewn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
                 if constexpr (PRE) {
                     if (use_pre) { prev[b][r] = pre[a][b][r]; continue; }
                 }
-                prev[b][r] = (src && i < g.M && j < g.N) ? src[i + j * lds_] : (TC)0;
+                prev[b][r] = (src && ((bmask >> b) & 1) && i < g.M && j < g.N) ? src[i + j * lds_] : (TC)0;
             }
         if (i >= g.M) continue;
 #pragma unroll
         for (int b = 0; b < TN; ++b)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t j = j0 + wn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
-                if (j >= g.N) continue;
+                const int64_t j = j0 + ewn * (BN / 2) + b * 16 + (sizeof(TC) == 8 ? g4 + 4 * r : 4 * g4 + r);
+                if (j >= g.N || !((bmask >> b) & 1)) continue;
                 if (PARTIAL) P[i + j * g.M] = acc[a][b][r] + prev[b][r];
                 else C[i + j * g.ldc] = (TC)g.alpha * acc[a][b][r] + (TC)g.beta * prev[b][r];
             }
     }
-    if (fold && tid < BM && i0 + tid < g.M) {
-        if (PARTIAL) ((TC*)g.Pc)[(int64_t)by * g.M + i0 + tid] = cpart;
-        else ((TC*)g.cvec)[i0 + tid] = cpart;
+    if (fold && fc >= 0 && fc < BM && i0 + fc < g.M) {
+        if (PARTIAL) ((TC*)g.Pc)[split * g.M + i0 + fc] = cpart;
+        else ((TC*)g.cvec)[i0 + fc] = cpart;
     }
 }
 
@@ -522,19 +583,23 @@ __device__ void GemmReduce<TC>::run(const GemmReduceArgs& a, int bx, int)
     const int bm = a.bm, bn = a.bn;
     const int64_t idx = (int64_t)bx * 256 + threadIdx.x;
     const TC* P = (const TC*)g.P;
+    const bool dsplit = g.lower && g.splits_diag > 0;
     if (idx < g.M * g.N) {
         const int64_t i = idx % g.M, j = idx / g.M;
-        if (!g.lower || (i / bm) >= (j / bn)) {
+        // lower-triangle products: the elements on and below the diagonal
+        if (!g.lower || i >= j) {
+            const int64_t nz = (dsplit && i / bm == j / bn) ? g.splits_diag : g.splits;
             TC s = 0;
-            for (int64_t z = 0; z < g.splits; ++z) s += P[z * g.M * g.N + idx];
+            for (int64_t z = 0; z < nz; ++z) s += P[z * g.M * g.N + idx];
             TC v = (TC)g.alpha * s;
             if (g.Cin) v += (TC)g.beta * ((const TC*)g.Cin)[i + j * g.ldcin];
             ((TC*)g.C)[i + j * g.ldc] = v;
         }
     }
     if (g.bvec && idx < g.M) {
+        const int64_t nz = dsplit ? g.splits_diag : g.splits;
         TC s = 0;
-        for (int64_t z = 0; z < g.splits; ++z) s += ((const TC*)g.Pc)[z * g.M + idx];
+        for (int64_t z = 0; z < nz; ++z) s += ((const TC*)g.Pc)[z * g.M + idx];
         ((TC*)g.cvec)[idx] = s;
     }
 }
@@ -599,6 +664,53 @@ void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int
     *splits = ceil_div(K, kc);
 }
 
+// Lower triangles in 128 x 128 tiles: the off-diagonal tiles keep their
+// split count sf, and the diagonal tiles, whose busiest wavefront carries 10
+// of the 16 MFMA blocks (see GemmCm::run), get a split count sd of their
+// own; (sf, sd) minimises the K tiles times MFMA blocks of the largest
+// work-group with all work-groups resident at once (two per CU), and is
+// taken when it beats the uniform plan by more than 1 %.
+void plan_splitk_gram(int64_t K, int64_t n, int lower, int64_t kchunk_fixed, int64_t* splits, int64_t* kchunk,
+                      int64_t* splits_diag, int64_t* kchunk_diag)
+{
+    plan_splitk(K, gemm_tiles(n, n, K, lower), splits, kchunk, kchunk_fixed);
+    *splits_diag = 0;
+    *kchunk_diag = 0;
+    if (!lower || kchunk_fixed > 0 || K < 2 * G_BK || tile_shape(n, n, K, lower).bm != 128) return;
+    const int64_t slots = 512;
+    const int64_t tm = ceil_div(n, 128), nf = tm * (tm - 1) / 2;
+    const int64_t kt = ceil_div(K, G_BK);
+    int64_t maxs = K / 128;
+    if (maxs < 1) maxs = 1;
+    const int64_t wg_u = (nf + tm) * *splits;
+    double best = (double)ceil_div(wg_u, slots) * 16.0 * (double)ceil_div(kt, *splits);
+    int64_t bf = 0, bd = 0;
+    for (int64_t sf = nf ? 1 : 0; sf <= maxs && nf * sf + tm <= slots; ++sf) {
+        int64_t sd = (slots - nf * sf) / tm;
+        if (sd > maxs) sd = maxs;
+        double c = 10.0 * (double)ceil_div(kt, sd);
+        if (nf) {
+            const double cf = 16.0 * (double)ceil_div(kt, sf);
+            if (cf > c) c = cf;
+        }
+        if (c < 0.99 * best) {
+            best = c;
+            bf = sf;
+            bd = sd;
+        }
+        if (!nf) break;
+    }
+    if (!bd) return;
+    if (nf) {
+        *kchunk = ceil_div(ceil_div(K, bf), G_BK) * G_BK;
+        *splits = ceil_div(K, *kchunk);
+    } else {
+        *splits = 1;
+    }
+    *kchunk_diag = ceil_div(ceil_div(K, bd), G_BK) * G_BK;
+    *splits_diag = ceil_div(K, *kchunk_diag);
+}
+
 template <typename TC>
 static void gemm_reduce_launch(Exec& ex, const GemmArgs& g)
 {
@@ -609,11 +721,11 @@ static void gemm_reduce_launch(Exec& ex, const GemmArgs& g)
 }
 
 template <typename TA, typename TB, typename TC, bool PARTIAL>
-static void gemm_tiles_launch(Exec& ex, const TileShape& ts, int64_t tiles, const GemmArgs& g)
+static void gemm_tiles_launch(Exec& ex, const TileShape& ts, int64_t gx, int64_t gy, const GemmArgs& g)
 {
-    if (ts.bm == 64) launch<GemmCm<TA, TB, TC, 64, 64, PARTIAL>>(ex, tiles, g.splits, g);
-    else if (ts.bn == 64) launch<GemmCm<TA, TB, TC, 128, 64, PARTIAL>>(ex, tiles, g.splits, g);
-    else launch<GemmCm<TA, TB, TC, 128, 128, PARTIAL>>(ex, tiles, g.splits, g);
+    if (ts.bm == 64) launch<GemmCm<TA, TB, TC, 64, 64, PARTIAL>>(ex, gx, gy, g);
+    else if (ts.bn == 64) launch<GemmCm<TA, TB, TC, 128, 64, PARTIAL>>(ex, gx, gy, g);
+    else launch<GemmCm<TA, TB, TC, 128, 128, PARTIAL>>(ex, gx, gy, g);
 }
 
 template <typename TA, typename TB, typename TC>
@@ -627,7 +739,7 @@ static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
     if (!partial) {
         g.splits = 1;
         g.xcd_remap = 0;
-        gemm_tiles_launch<TA, TB, TC, false>(ex, ts, tiles, g);
+        gemm_tiles_launch<TA, TB, TC, false>(ex, ts, tiles, 1, g);
         return;
     }
     if (g.splits < 1) g.splits = 1;
@@ -635,7 +747,15 @@ static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
     // (lower-triangle products only: on the FP64 sketch product, whose
     // grid is several waves of work-groups, it made the launch slower)
     g.xcd_remap = !ex.recording() && g.splits > 1 && g.lower;
-    gemm_tiles_launch<TA, TB, TC, true>(ex, ts, tiles, g);
+    if (g.lower && g.splits_diag > 0) {
+        // one-dimensional grid: diagonal tiles x splits_diag, then the tiles
+        // below the diagonal x splits
+        const int64_t tm = ceil_div(g.M, (int64_t)ts.bm);
+        g.xcd_remap = !ex.recording();
+        gemm_tiles_launch<TA, TB, TC, true>(ex, ts, tm * g.splits_diag + (tiles - tm) * g.splits, 1, g);
+    } else {
+        gemm_tiles_launch<TA, TB, TC, true>(ex, ts, tiles, g.splits, g);
+    }
     if (reduce) gemm_reduce_launch<TC>(ex, g);
 }
 

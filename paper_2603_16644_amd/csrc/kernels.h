@@ -75,6 +75,9 @@ struct GemmArgs {
     void* P; int accumulate_partials;
     const void* bvec; void* Pc; void* cvec;
     int xcd_remap;    // set by the launcher (direct split-K lower-triangle launches)
+    // lower-triangle split-K only: the diagonal tiles cut K into splits_diag
+    // chunks of kchunk_diag (0: as the other tiles); see plan_splitk_gram
+    int64_t splits_diag, kchunk_diag;
 };
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
 void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce
@@ -87,6 +90,13 @@ void gemm_ddf(Exec& ex, const GemmArgs& g);           // fl32(A)^T fl32(B) etc.
 // tiles (kchunk_fixed > 0: fixed chunk length, for batches)
 void plan_splitk(int64_t K, int64_t tiles, int64_t* splits, int64_t* kchunk, int64_t kchunk_fixed = 0);
 int64_t gemm_tiles(int64_t M, int64_t N, int64_t K, int lower);
+// split-K plan of the FP64 Gram product (n x n, K = m; lower-triangle tiles
+// when `lower`): plan_splitk, or for lower triangles in 128 x 128 tiles a
+// separate split of the diagonal tiles (whose wavefronts carry less MFMA
+// work) when that shortens the largest work-group.  Partial buffers hold
+// max(splits, splits_diag) slices.
+void plan_splitk_gram(int64_t K, int64_t n, int lower, int64_t kchunk_fixed, int64_t* splits, int64_t* kchunk,
+                      int64_t* splits_diag, int64_t* kchunk_diag);
 
 // ---------------------------------------------------------------- TRSM / factorizations
 // Ap = A R^{-1}, R upper n x n (FP64), blocked substitution.

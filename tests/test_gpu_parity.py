@@ -251,6 +251,36 @@ def test_gram_and_factors_elementwise(pne, orc, hpne):
         np.testing.assert_allclose(Lg, Lo, rtol=0, atol=1e-8 * np.abs(Lo).max())
 
 
+_GRAM128 = {}   # m -> (A, b, oracle C, oracle c), shared by the PNE and HPNE cases
+
+
+@pytest.mark.parametrize("hpne", [False, True])
+@pytest.mark.parametrize("m", [6000, 5999])
+def test_gram_128_tiles_elementwise(pne, orc, hpne, m):
+    """Gram products of order above 512, which run in 128 x 128 tiles: K
+    tiles copied straight into LDS when the leading dimension is even, the
+    register-staged loop when it is odd (and for the ragged last K chunk);
+    for PNE the diagonal tiles cut K apart from the others and split their
+    lower triangles between the four wavefronts.  n = 700 leaves a partial
+    last tile.  R = I makes A_p = A exactly, so only the summation order
+    differs from the oracle's product (bound m u sum |a_ki| |a_kj|)."""
+    n = 700
+    if m not in _GRAM128:
+        rng = np.random.default_rng(1021 + m)
+        A = rng.standard_normal((m, n))
+        b = rng.standard_normal(m)
+        _GRAM128[m] = (A, b) + orc.gram(A, A, b)
+    A, b, Co, co = _GRAM128[m]
+    Cg, cg, _, info = pne.pne_gram(dev(A), torch.from_numpy(b).cuda(), dev(np.eye(n)), hpne=hpne, factor=False)
+    assert int(host(info)[0]) == 0
+    Cg, cg = host(Cg), host(cg)
+    mag = np.abs(A).T @ np.abs(A)
+    sel = np.ones((n, n), bool) if hpne else np.tril(np.ones((n, n), bool))
+    assert np.all(np.abs(Cg - Co)[sel] <= m * 1.2e-16 * mag[sel])
+    magc = np.abs(A).T @ np.abs(b)
+    assert np.all(np.abs(cg - co) <= m * 1.2e-16 * magc)
+
+
 @pytest.mark.parametrize("hpne", [False, True])
 @pytest.mark.parametrize("col", [0, 21, 70, 99])
 def test_factor_breakdown_reports_column(pne, orc, hpne, col):
