@@ -71,6 +71,10 @@ struct Buffers {
     int32_t* choice;
 };
 
+// Leading dimension of A_p: m rounded up to even, so that its columns start
+// on 16-byte boundaries (16-byte loads in its products).
+int64_t ap_ld(int64_t m) { return (m + 1) & ~(int64_t)1; }
+
 size_t scratch_bytes(const Problem& p, int sk, int qr)
 {
     size_t b = p.sketch_kind == 1 ? srft_workspace_bytes(p.m, p.n, srft_prec(sk))
@@ -110,7 +114,7 @@ size_t layout(const Problem& p, void* base, size_t cap, Buffers* out, bool with_
     b.scratch = ar.take<char>(scr);
     b.W = ar.take<char>((size_t)p.s * p.n * (any64 ? 8 : 4));
     b.R = ar.take<double>((size_t)p.n * p.n);
-    b.Ap = ar.take<double>((size_t)p.m * p.n);
+    b.Ap = ar.take<double>((size_t)ap_ld(p.m) * p.n);
     b.C = ar.take<double>((size_t)p.n * p.n);
     b.c = ar.take<double>(p.n);
     b.piv = ar.take<int32_t>(p.n);
@@ -248,15 +252,16 @@ void run_gram(Exec& ex, const Problem& p, const double* dA, const double* db, co
     const int64_t m = p.m, n = p.n, lda = p.lda;
     const int hpne = p.hpne;
     ex.stage(ST_TRSM);
-    trsm_right_upper(ex, m, n, dA, lda, b.R, n, b.Ap, m);
+    const int64_t ldap = ap_ld(m);
+    trsm_right_upper(ex, m, n, dA, lda, b.R, n, b.Ap, ldap);
     mark(ex, PH_TRSM);
     ex.stage(ST_GRAM);
     int64_t splits, kc, sd, kcd;
     plan_splitk_gram(m, n, !hpne, ex.kchunk_fixed, &splits, &kc, &sd, &kcd);
     GemmArgs g{};
     g.M = n; g.N = n; g.K = m;
-    g.A = b.Ap; g.lda = m; g.transA = 1;
-    g.B = hpne ? (const void*)dA : (const void*)b.Ap; g.ldb = hpne ? lda : m; g.transB = 0;
+    g.A = b.Ap; g.lda = ldap; g.transA = 1;
+    g.B = hpne ? (const void*)dA : (const void*)b.Ap; g.ldb = hpne ? lda : ldap; g.transB = 0;
     g.alpha = 1.0; g.beta = 0.0;
     g.C = b.C; g.ldc = n;
     g.lower = !hpne;
@@ -310,7 +315,7 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     for (int k = 0; k < p.refine; ++k) {
         ex.iter((uint32_t)k);
         residual(ex, m, n, dA, lda, db, dx, b.r);
-        gemv_t(ex, m, n, b.Ap, m, b.r, b.y, b.gv);
+        gemv_t(ex, m, n, b.Ap, ap_ld(m), b.r, b.y, b.gv);
         if (hpne) lu_solve_lb(ex, n, b.C, n, b.piv, b.dinv1, b.dinv2, b.y, b.d, b.flags, dinfo);
         else pne_solve_lb(ex, n, b.C, n, b.dinv1, b.Lt, b.dinv1t, b.R, n, b.dinv2, b.y, b.d, b.t, b.flags, dinfo);
         axpy_update(ex, n, dx, b.d);

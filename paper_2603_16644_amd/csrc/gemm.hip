@@ -6,9 +6,7 @@
 // C = alpha op(A) op(B) + beta Cin on 128 x BN output tiles (BN = 64 or 128),
 // 256 threads = 2 x 2 waves, MFMA 16x16x4 (v_mfma_f64_16x16x4f64 or
 // v_mfma_f32_16x16x4f32), K staged through LDS 16 deep with the next K tile
-// prefetched into registers, or, for the FP64 Gram products (both operands
-// stored with K contiguous), copied from memory straight into LDS.  The MFMA
-// operands are fed swapped (op(B)^T as
+// prefetched into registers.  The MFMA operands are fed swapped (op(B)^T as
 // the instruction's A, op(A)^T as its B) so that lane l owns output rows
 // i = l % 16: consecutive lanes write consecutive addresses of the
 // column-major result.  Output layout of the 16x16 result in lane l,
@@ -241,62 +239,19 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
         }
     }
 
-    // Direct-to-LDS path (FP64, 128 x 128 tiles, op(A) = A^T and op(B) = B:
-    // both operands stored with K contiguous, as in the Gram products).  The
-    // K tiles go from memory straight into LDS (global_load_lds_dwordx4, no
-    // register staging and no LDS stores), two buffers, one barrier per tile.
-    // LDS tile of an operand: 128 columns (rows of C) x 16 K values, 128 B
-    // per column; 16-byte slot s of column c holds the K pair
-    // s ^ ((c >> 1) & 7), so that the 16 lanes of a 16-byte read (16
-    // consecutive columns, one K pair) hit 16 different bank groups.  The
-    // MFMA of step s takes K = 4 (l / 16) + s in lane l (any assignment of
-    // the 16 K values to (step, lane group) gives the same sum as long as
-    // both operands use it), so each lane reads its four K values of a column
-    // as two 16-byte loads.
-    bool dma = false;
-    if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128)
-        dma = g.transA && !g.transB && vecA && vecB && ((kend - kbeg) % G_BK) == 0 && kend - kbeg >= 2 * G_BK &&
-              (kbeg & 1) == 0 && g.lda < (INT64_C(1) << 22) && g.ldb < (INT64_C(1) << 22);
-    if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128) {
-      if (dma) {
-        typedef __attribute__((address_space(3))) void* lds_ptr;
-        // per-lane source offsets of the four 1 KB chunks this wavefront
-        // moves per operand (chunk I = columns 8 I .. 8 I + 7; columns past
-        // the matrix read its last column, whose results are never stored)
-        // (byte offsets from the tile's first column, 32-bit: the launch
-        // requires 128 columns of either operand to span less than 4 GiB)
-        uint32_t offa[4], offb[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const int c = 8 * (w * 4 + j) + (lane >> 3);
-            const int kp = (lane & 7) ^ ((c >> 1) & 7);
-            const int64_t ca = (i0 + c < g.M) ? c : g.M - 1 - i0;
-            const int64_t cb = (j0 + c < g.N) ? c : g.N - 1 - j0;
-            offa[j] = (uint32_t)((ca * g.lda + 2 * kp) * 8);
-            offb[j] = (uint32_t)((cb * g.ldb + 2 * kp) * 8);
-        }
-        const char* abase = (const char*)(A + i0 * g.lda);
-        const char* bbase = (const char*)(B + j0 * g.ldb);
-        auto dma_tile = [&](int64_t k0, int b) {
-            const char* pa = abase + k0 * 8;
-            const char* pb = bbase + k0 * 8;
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                const int I = w * 4 + j;
-                __builtin_amdgcn_global_load_lds((const void*)(pa + offa[j]), (lds_ptr)(As[b] + I * 128), 16, 0, 0);
-                __builtin_amdgcn_global_load_lds((const void*)(pb + offb[j]), (lds_ptr)(Bs[b] + I * 128), 16, 0, 0);
-            }
-        };
-        // Diagonal tiles of a lower-triangle product: the two wavefronts on
-        // the diagonal take the lower triangles of their quadrants (10 of 16
-        // MFMA blocks), and the other two split the quadrant below the
-        // diagonal by 32-column halves (8 blocks each), so that no SIMD
-        // carries more than 10 blocks; nobody computes the quadrant above
-        // the diagonal.  role: 0 = whole quadrant, 1 = lower triangle,
-        // 2 / 3 = left / right half.  The fold runs on the two half
-        // wavefronts.
-        int role = 0;
-        if (g.lower && ti == tj) {
+    // Diagonal tiles of a lower-triangle product (FP64, 128 x 128 tiles,
+    // split-K, direct launches): the two wavefronts on the diagonal take
+    // the lower triangles of their quadrants (10 of 16 MFMA blocks), and the
+    // other two split the quadrant below the diagonal into 32-column halves
+    // (8 blocks each), so that no SIMD carries more than 10 blocks per K
+    // step; nobody computes the quadrant above the diagonal.  role: 0 =
+    // whole quadrant, 1 = lower triangle, 2 / 3 = left / right half.  The
+    // fold runs on the two half wavefronts.  (Grouped batch launches keep
+    // the plain layout, with the wavefront above the diagonal idle.)
+    constexpr bool ROLES_T = sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 128 && BN == 128 && PARTIAL;
+    int role = 0;
+    if constexpr (ROLES_T) {
+        if (g.diag_roles && g.lower && ti == tj) {
             if (wm == wn) role = 1;
             else {
                 ewm = 1;
@@ -307,81 +262,6 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
             fc = tid - 64;
         }
         role = __builtin_amdgcn_readfirstlane(role);   // (uniform per wavefront)
-        const bool fthr = fold && fc >= 0 && fc < BM;
-        const int sw = (r16 >> 1) & 7;   // swizzle of every column this lane reads
-        double2 xa[TM][2], xb[TN][2];
-        auto read_ops = [&](int b) {
-            const TC* as = As[b];
-            const TC* bs = Bs[b];
-#pragma unroll
-            for (int t = 0; t < TM; ++t) {
-                const int c = ewm * 64 + t * 16 + r16;
-                xa[t][0] = *(const double2*)(as + c * 16 + ((2 * g4) ^ sw) * 2);
-                xa[t][1] = *(const double2*)(as + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
-            }
-#pragma unroll
-            for (int t = 0; t < TN; ++t) {
-                const int c = ewn * 64 + t * 16 + r16;
-                xb[t][0] = *(const double2*)(bs + c * 16 + ((2 * g4) ^ sw) * 2);
-                xb[t][1] = *(const double2*)(bs + c * 16 + ((2 * g4 + 1) ^ sw) * 2);
-            }
-        };
-        auto mfma_ops = [&](auto rl) {
-            constexpr int RL = decltype(rl)::value;
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-#pragma unroll
-                for (int a = 0; a < TM; ++a)
-#pragma unroll
-                    for (int b2 = 0; b2 < TN; ++b2) {
-                        if (RL == 1 && a < b2) continue;
-                        if (RL == 2 && b2 >= TN / 2) continue;
-                        if (RL == 3 && b2 < TN / 2) continue;
-                        const double fa = (s & 1) ? xa[a][s >> 1].y : xa[a][s >> 1].x;
-                        const double fb = (s & 1) ? xb[b2][s >> 1].y : xb[b2][s >> 1].x;
-                        acc[a][b2] = mfma_cm<TC>(fb, fa, acc[a][b2]);
-                    }
-        };
-        // op(A) b by the folding work-groups: thread fthr sums column fc of
-        // the tile in K order
-        auto fold_dma = [&](int b, int64_t k0) {
-            if (fthr) {
-                const TC* as = As[b] + fc * 16;
-                const int sv = (fc >> 1) & 7;
-#pragma unroll
-                for (int kp = 0; kp < 8; ++kp) {
-                    const double2 v = *(const double2*)(as + (kp ^ sv) * 2);
-                    cpart += v.x * (TC)bv[k0 + 2 * kp];
-                    cpart += v.y * (TC)bv[k0 + 2 * kp + 1];
-                }
-            }
-        };
-        // Per tile: wait for its copies, barrier, read the MFMA operands and
-        // the fold's column out of LDS, then start the copies of the next
-        // tile into the other buffer and run the MFMAs while they fly (the
-        // copies come after every LDS read of the step, so no wait for them
-        // is needed before those reads).
-        const int64_t nk = (kend - kbeg) / G_BK;
-        // one copy of the K loop per role
-        auto kloop = [&](auto rl) {
-            dma_tile(kbeg, 0);
-            for (int64_t t = 0; t < nk; ++t) {
-                const int b = (int)(t & 1);
-                __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0): this thread's copies of tile t are in LDS
-                __syncthreads();                      // everyone's; and buffer b ^ 1 is no longer read
-                read_ops(b);
-                fold_dma(b, kbeg + t * G_BK);
-                if (t + 1 < nk) dma_tile(kbeg + (t + 1) * G_BK, b ^ 1);
-                mfma_ops(rl);
-            }
-        };
-        switch (role) {
-        case 0: kloop(std::integral_constant<int, 0>{}); break;
-        case 1: kloop(std::integral_constant<int, 1>{}); break;
-        case 2: kloop(std::integral_constant<int, 2>{}); break;
-        default: kloop(std::integral_constant<int, 3>{}); break;
-        }
-      }
     }
 
     // Fast path (FP64 operands, full tile off the diagonal of a lower-
@@ -392,8 +272,7 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
     // that the scheduler can interleave them and the MFMA pipe keeps running
     // while they issue.  64 x 64 tiles only: on the products of A R^-1 it
     // raised the MFMA busy share from 57 % to 64 %, while the 128 x 128
-    // tiles of the Gram product ran slower with it (61 % against 64 %; they
-    // take the direct-to-LDS path above).
+    // tiles of the Gram product ran slower with it (61 % against 64 %).
     bool fast = false;
     if constexpr (sizeof(TA) == 8 && sizeof(TB) == 8 && sizeof(TC) == 8 && BM == 64)
         fast = vecA && vecB && i0 + BM <= g.M && j0 + BN <= g.N && ((kend - kbeg) % G_BK) == 0 &&
@@ -488,10 +367,97 @@ __device__ void GemmCm<TA, TB, TC, BM, BN, PARTIAL>::run(const GemmArgs& g, int 
       }
     }
 
+    // Gram tiles (FP64, 128 x 128, op(A) = A^T and op(B) = B: both operands
+    // stored with K contiguous, 16-byte aligned, whole K tiles): the loop
+    // below without bounds checks (columns past the matrix read its last
+    // column, whose results are never stored), one copy per role.
+    bool gram = false;
+    if constexpr (ROLES_T)
+        gram = g.transA && !g.transB && vecA && vecB && ((kend - kbeg) % G_BK) == 0 && kend - kbeg >= 2 * G_BK;
+    if constexpr (ROLES_T) {
+      if (gram) {
+        const int ii = tid >> 1, kb = (tid & 1) * APT;   // row of op(A) / column of op(B), K offset
+        const int64_t ca = (i0 + ii < g.M) ? i0 + ii : g.M - 1;
+        const int64_t cb = (j0 + ii < g.N) ? j0 + ii : g.N - 1;
+        const TA* __restrict__ pa0 = A + ca * g.lda + kb;
+        const TB* __restrict__ pb0 = B + cb * g.ldb + kb;
+        double2 va[APT / 2], vb[BPT / 2];
+        auto gl = [&](int64_t k0) {
+#pragma unroll
+            for (int q = 0; q < APT / 2; ++q) va[q] = *(const double2*)(pa0 + k0 + 2 * q);
+#pragma unroll
+            for (int q = 0; q < BPT / 2; ++q) vb[q] = *(const double2*)(pb0 + k0 + 2 * q);
+        };
+        auto ss = [&](int b) {
+#pragma unroll
+            for (int q = 0; q < APT; ++q) As[b][(kb + q) * LDA_S + ii] = (q & 1) ? va[q / 2].y : va[q / 2].x;
+#pragma unroll
+            for (int q = 0; q < BPT; ++q) Bs[b][(kb + q) * LDB_S + ii] = (q & 1) ? vb[q / 2].y : vb[q / 2].x;
+        };
+        auto gloop = [&](auto rl) {
+            constexpr int RL = decltype(rl)::value;
+            const int64_t nk = (kend - kbeg) / G_BK;
+            gl(kbeg);
+            ss(0);
+            gl(kbeg + G_BK);
+            int b = 0;
+            for (int64_t t = 0; t < nk; ++t) {
+                __syncthreads();
+                const TC* as = As[b];
+                const TC* bs = Bs[b];
+#pragma unroll
+                for (int kk = 0; kk < G_BK; kk += 4) {
+                    if (RL == 0 && idle) break;
+                    TC fa[TM], fb[TN];
+#pragma unroll
+                    for (int u = 0; u < TM; ++u) fa[u] = as[(kk + g4) * LDA_S + ewm * (BM / 2) + u * 16 + r16];
+#pragma unroll
+                    for (int u = 0; u < TN; ++u) fb[u] = bs[(kk + g4) * LDB_S + ewn * (BN / 2) + u * 16 + r16];
+#pragma unroll
+                    for (int a = 0; a < TM; ++a)
+#pragma unroll
+                        for (int c = 0; c < TN; ++c) {
+                            if (RL == 1 && a < c) continue;
+                            if (RL == 2 && c >= TN / 2) continue;
+                            if (RL == 3 && c < TN / 2) continue;
+                            acc[a][c] = mfma_cm<TC>(fb[c], fa[a], acc[a][c]);
+                        }
+                }
+                // op(A) b, b read directly (uniform addresses: scalar loads)
+                if (fold && fc >= 0 && fc < BM) {
+                    const int64_t k0 = kbeg + t * G_BK;
+#pragma unroll
+                    for (int kk = 0; kk < G_BK; ++kk) cpart += as[kk * LDA_S + fc] * (TC)bv[k0 + kk];
+                }
+                if (t + 1 < nk) {
+                    ss(b ^ 1);
+                    if (t + 2 < nk) gl(kbeg + (t + 2) * G_BK);
+                }
+                b ^= 1;
+            }
+        };
+        switch (role) {
+        case 0: gloop(std::integral_constant<int, 0>{}); break;
+        case 1: gloop(std::integral_constant<int, 1>{}); break;
+        case 2: gloop(std::integral_constant<int, 2>{}); break;
+        default: gloop(std::integral_constant<int, 3>{}); break;
+        }
+        fast = true;   // (the K loop has run)
+      }
+    }
+
     // Pipeline: tile t is in LDS buffer t % 2 while tile t + 1 is being
-    // loaded into registers; one barrier per tile.
+    // loaded into registers; one barrier per tile.  (A diagonal tile whose
+    // K chunk takes this loop keeps the plain wavefront layout.)
+    if constexpr (ROLES_T) {
+        if (!fast && role != 0) {
+            ewm = wm;
+            ewn = wn;
+            bmask = (1 << TN) - 1;
+            fc = tid;
+        }
+    }
     int buf = 0;
-    if (dma) fast = true;   // (its K loop has run)
     if (!fast && kbeg < kend) {
         gload(kbeg);
         sstore(0);
@@ -747,6 +713,8 @@ static void gemm_launch(Exec& ex, const GemmArgs& g0, bool reduce)
     // (lower-triangle products only: on the FP64 sketch product, whose
     // grid is several waves of work-groups, it made the launch slower)
     g.xcd_remap = !ex.recording() && g.splits > 1 && g.lower;
+    // (direct launches only; see GemmCm::run)
+    g.diag_roles = !ex.recording();
     if (g.lower && g.splits_diag > 0) {
         // one-dimensional grid: diagonal tiles x splits_diag, then the tiles
         // below the diagonal x splits

@@ -78,6 +78,7 @@ struct GemmArgs {
     // lower-triangle split-K only: the diagonal tiles cut K into splits_diag
     // chunks of kchunk_diag (0: as the other tiles); see plan_splitk_gram
     int64_t splits_diag, kchunk_diag;
+    int diag_roles;   // set by the launcher: split the diagonal tiles' work over all wavefronts
 };
 // element types: d = double, f = float; "ddf" = A, B stored double, computed in float
 void gemm_f64(Exec& ex, const GemmArgs& g);           // full path incl. reduce

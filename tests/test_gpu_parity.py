@@ -251,26 +251,27 @@ def test_gram_and_factors_elementwise(pne, orc, hpne):
         np.testing.assert_allclose(Lg, Lo, rtol=0, atol=1e-8 * np.abs(Lo).max())
 
 
-_GRAM128 = {}   # m -> (A, b, oracle C, oracle c), shared by the PNE and HPNE cases
+_GRAMS = {}   # (m, n) -> (A, b, oracle C, oracle c), shared by the PNE and HPNE cases
 
 
 @pytest.mark.parametrize("hpne", [False, True])
-@pytest.mark.parametrize("m", [6000, 5999])
-def test_gram_128_tiles_elementwise(pne, orc, hpne, m):
-    """Gram products of order above 512, which run in 128 x 128 tiles: K
-    tiles copied straight into LDS when the leading dimension is even, the
-    register-staged loop when it is odd (and for the ragged last K chunk);
-    for PNE the diagonal tiles cut K apart from the others and split their
-    lower triangles between the four wavefronts.  n = 700 leaves a partial
-    last tile.  R = I makes A_p = A exactly, so only the summation order
-    differs from the oracle's product (bound m u sum |a_ki| |a_kj|)."""
-    n = 700
-    if m not in _GRAM128:
+@pytest.mark.parametrize("m,n", [(6000, 700), (5999, 700), (6001, 300)])
+def test_gram_split_k_tiles_elementwise(pne, orc, hpne, m, n):
+    """Split-K Gram products with K above 4096: order 700 in 128 x 128 tiles,
+    order 300 in 64 x 64 tiles.  A_p's leading dimension is m rounded up to
+    even, so its K tiles take the 16-byte loads of the Gram loop; HPNE's
+    second operand A keeps the caller's leading dimension, and an odd one
+    takes the general loop (as does a ragged last K chunk).  For PNE in
+    128 x 128 tiles the diagonal tiles split their lower triangles between
+    the four wavefronts and cut K apart from the others.  Both orders leave
+    a partial last tile.  R = I makes A_p = A exactly, so only the summation
+    order differs from the oracle's product (bound m u sum |a_ki| |a_kj|)."""
+    if (m, n) not in _GRAMS:
         rng = np.random.default_rng(1021 + m)
         A = rng.standard_normal((m, n))
         b = rng.standard_normal(m)
-        _GRAM128[m] = (A, b) + orc.gram(A, A, b)
-    A, b, Co, co = _GRAM128[m]
+        _GRAMS[(m, n)] = (A, b) + orc.gram(A, A, b)
+    A, b, Co, co = _GRAMS[(m, n)]
     Cg, cg, _, info = pne.pne_gram(dev(A), torch.from_numpy(b).cuda(), dev(np.eye(n)), hpne=hpne, factor=False)
     assert int(host(info)[0]) == 0
     Cg, cg = host(Cg), host(cg)
