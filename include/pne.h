@@ -31,7 +31,8 @@
  *     Cholesky of the PNE matrix broke down at column k; 3000+k: zero or
  *     non-finite pivot in the LU of the HPNE matrix at column k (k 1-based);
  *     4000+k: a block of the parallel triangular solves gave up waiting for
- *     block k (a scheduling failure; the result is invalid).  R_s(k,k) counts
+ *     block k (a scheduling failure; the result is invalid); 5000: A or b
+ *     holds a non-finite entry (only with pne_opts.check_finite, see there).  R_s(k,k) counts
  *     as zero when it is not finite.  On failure x is filled with NaN; no
  *     silent fallback to another precision is taken.
  *   - Same inputs and options give bitwise identical results (every
@@ -83,6 +84,13 @@ typedef struct {
                                trigonometric transform of Section 6.2 (see pne_sketch_srft);
                                with SRFT an FP16 sketch precision runs as FP32, FP8 is not
                                supported                                                    */
+    int32_t check_finite;   /* nonzero: scan A (its m x n entries) and b for NaN or
+                               infinity before anything else is enqueued; if one is
+                               found the call writes 5000 to *dinfo and returns
+                               PNE_EINVAL without solving (batched calls: per member,
+                               PNE_EINVAL if any member fails).  The scan is read back,
+                               so the call then synchronises its stream once; not for
+                               use under stream capture.  Default 0.                    */
 } pne_opts;
 
 typedef struct {
@@ -94,7 +102,7 @@ typedef struct {
 
 /* Fills *opts with the defaults: s = 0 (3n), seed = 0, problem_id = 0,
  * sketch_prec = qr_prec = AUTO, known_kappa = 0, refine_steps = 1,
- * block_rows = 128, cond_method = 0, sketch_kind = 0. */
+ * block_rows = 128, cond_method = 0, sketch_kind = 0, check_finite = 0. */
 void pne_default_opts(pne_opts* opts);
 
 /* Bytes of workspace pne_solve (hpne = 0) or hpne_solve (hpne = 1) needs for

@@ -46,7 +46,7 @@ class Opts(ctypes.Structure):
                 ("sketch_prec", ctypes.c_int32), ("qr_prec", ctypes.c_int32),
                 ("known_kappa", ctypes.c_double), ("refine_steps", ctypes.c_int32),
                 ("block_rows", ctypes.c_int32), ("cond_method", ctypes.c_int32),
-                ("sketch_kind", ctypes.c_int32)]
+                ("sketch_kind", ctypes.c_int32), ("check_finite", ctypes.c_int32)]
 
 
 class Info(ctypes.Structure):
@@ -129,7 +129,7 @@ def lib():
 
 def make_opts(s: int = 0, seed: int = 0, problem_id: int = 0, sketch_prec="auto", qr_prec=None,
               known_kappa: float = 0.0, refine_steps: int = 1, block_rows: int = 128,
-              cond_method: int = 0, sketch_kind="gaussian") -> Opts:
+              cond_method: int = 0, sketch_kind="gaussian", check_finite: bool = False) -> Opts:
     o = Opts()
     lib().pne_default_opts(ctypes.byref(o))
     o.s = int(s)
@@ -143,6 +143,7 @@ def make_opts(s: int = 0, seed: int = 0, problem_id: int = 0, sketch_prec="auto"
     o.block_rows = int(block_rows)
     o.cond_method = int(cond_method)
     o.sketch_kind = {"gaussian": 0, "srft": 1}[sketch_kind] if isinstance(sketch_kind, str) else int(sketch_kind)
+    o.check_finite = int(bool(check_finite))
     return o
 
 

@@ -326,6 +326,25 @@ pne_status run_solve(Exec& ex, const Problem& p, const double* dA, const double*
     return PNE_OK;
 }
 
+// pne_opts::check_finite: each problem's A (m x n, ld lda) and b scanned
+// for non-finite entries (AllFinite writes 5000 to its info word), the info
+// words read back; PNE_EINVAL if any is set.
+pne_status check_finite_inputs(hipStream_t st, int64_t count, const int64_t* m, const int64_t* n,
+                               const double* const* A, const int64_t* lda, const double* const* b, int32_t* dinfo)
+{
+    Exec ex;
+    ex.st = st;
+    zero_i32(ex, count, dinfo);
+    for (int64_t i = 0; i < count; ++i) all_finite(ex, m[i], n[i], A[i], lda[i], b[i], dinfo + i);
+    std::vector<int32_t> h((size_t)count);
+    if (hipMemcpyAsync(h.data(), dinfo, (size_t)count * sizeof(int32_t), hipMemcpyDeviceToHost, st) != hipSuccess)
+        return PNE_EHIP;
+    if (hipStreamSynchronize(st) != hipSuccess) return PNE_EHIP;
+    for (int32_t v : h)
+        if (v != 0) return PNE_EINVAL;
+    return PNE_OK;
+}
+
 pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t lda, const double* db,
                       double* dx, const pne_opts* o, void* dwork, size_t work_bytes, int32_t* dinfo,
                       pne_info* hinfo, hipStream_t st)
@@ -340,6 +359,10 @@ pne_status solve_impl(int hpne, int64_t m, int64_t n, const double* dA, int64_t 
     if (work_bytes < need) return PNE_EWORKSPACE;
     Exec ex;
     ex.st = st;
+    if (o->check_finite) {
+        const pne_status fc = check_finite_inputs(st, 1, &m, &n, &dA, &lda, &db, dinfo);
+        if (fc) return fc;
+    }
     prof_reset();
     prof_mark(PH_START, st);
     ex.stage(ST_INIT);
@@ -631,6 +654,20 @@ pne_status solve_batched(int64_t batch, const pne_problem_desc* hd, const double
 {
     pne_status chk = check_batch(batch, hd, o, hpne);
     if (chk) return chk;
+    if (o->check_finite) {
+        if (!dA_base || !db_base || !dinfo) return PNE_EINVAL;
+        std::vector<int64_t> m(batch), n(batch), lda(batch);
+        std::vector<const double*> A(batch), b(batch);
+        for (int64_t i = 0; i < batch; ++i) {
+            m[i] = hd[i].m;
+            n[i] = hd[i].n;
+            lda[i] = hd[i].lda;
+            A[i] = dA_base + hd[i].a_offset;
+            b[i] = db_base + hd[i].b_offset;
+        }
+        const pne_status fc = check_finite_inputs(st, batch, m.data(), n.data(), A.data(), lda.data(), b.data(), dinfo);
+        if (fc) return fc;
+    }
     pne_batch_plan_s* plan = nullptr;
     pne_status rc = plan_create(batch, hd, dA_base, db_base, dx_base, o, hpne, dwork, work_bytes, dinfo, st,
                                 batch_tune(batch, hd, o, hpne), &plan);
@@ -680,6 +717,7 @@ void pne_default_opts(pne_opts* o)
     o->block_rows = 128;
     o->cond_method = 0;
     o->sketch_kind = 0;
+    o->check_finite = 0;
 }
 
 const char* pne_status_string(pne_status st)

@@ -167,6 +167,8 @@ void fill_nan_on_info(Exec& ex, int64_t n, double* x, const int32_t* info);
 // dst(:, j) = src(:, j) for an r x c column-major block
 void copy_f64(Exec& ex, int64_t r, int64_t c, const double* src, int64_t lds, double* dst, int64_t ldd);
 void zero_i32(Exec& ex, int64_t n, int32_t* p);
+// *info = 5000 if A (m x n, ld lda) or b (m) holds a NaN or an infinity
+void all_finite(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* b, int32_t* info);
 void copy_i32(Exec& ex, int64_t n, const int32_t* src, int32_t* dst);
 
 // ---------------------------------------------------------------- batches

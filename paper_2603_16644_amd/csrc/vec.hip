@@ -508,4 +508,44 @@ void copy_i32(Exec& ex, int64_t n, const int32_t* src, int32_t* dst)
     launch<CopyI32>(ex, ceil_div(n, 256), 1, CopyI32::Args{n, src, dst});
 }
 
+// Input scan of pne_opts::check_finite: the m x n entries of A and the m of
+// b, a grid-stride loop over both; any thread that meets a NaN or an
+// infinity stores 5000 (every such store writes the same value).
+struct AllFiniteArgs {
+    int64_t m, n;
+    const double* A;
+    int64_t lda;
+    const double* b;
+    int32_t* info;
+    int64_t stride;   // threads of the launch
+};
+struct AllFinite {
+    typedef AllFiniteArgs Args;
+    static constexpr int NTH = 256, WPE = 0;
+    static __device__ void run(const AllFiniteArgs& a, int bx, int)
+    {
+        const int64_t mn = a.m * a.n;
+        bool bad = false;
+        for (int64_t e = (int64_t)bx * NTH + threadIdx.x; e < mn + a.m; e += a.stride) {
+            double v;
+            if (e < mn) {
+                const int64_t j = e / a.m;
+                v = a.A[(e - j * a.m) + j * a.lda];
+            } else {
+                v = a.b[e - mn];
+            }
+            bad = bad || !isfinite(v);
+        }
+        if (bad) *a.info = 5000;
+    }
+};
+
+void all_finite(Exec& ex, int64_t m, int64_t n, const double* A, int64_t lda, const double* b, int32_t* info)
+{
+    int64_t g = ceil_div(m * n + m, (int64_t)AllFinite::NTH * 8);
+    if (g > 4096) g = 4096;
+    if (g < 1) g = 1;
+    launch<AllFinite>(ex, g, 1, AllFiniteArgs{m, n, A, lda, b, info, g * AllFinite::NTH});
+}
+
 }  // namespace pne

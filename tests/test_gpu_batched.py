@@ -316,3 +316,45 @@ def test_batch512_sampled_members_within_qr_error(pne):
         if not e <= 10 * e_qr:
             bad.append((i, p.m, p.n, p.kappa, p.rho, e, e_qr))
     assert not bad, bad
+
+
+def test_batch_repeatable_bitwise(pne):
+    """128 members of the batch distribution (m up to 50000, n up to 512:
+    tens of thousands of work-groups per grouped launch), solved four times
+    into the same output: every run gives the same x bit for bit and no info
+    code.  The sums of the library run in a fixed order, so a difference can
+    only come from a race between work-groups."""
+    shapes = draw_batch_shapes(128, 3)
+    probs = [make_problem(m, n, k, r, seed=50000 + i, device="cuda") for i, (m, n, k, r) in enumerate(shapes)]
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=0, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    x0 = None
+    for _ in range(4):
+        x.fill_(float("nan"))
+        info = host(pne.pne_solve_batched(A, b, x, descs, opts=o))
+        assert np.all(info == 0)
+        xr = host(x).copy()
+        if x0 is None:
+            x0 = xr
+        else:
+            assert np.array_equal(xr, x0)
+
+
+def test_batched_check_finite(pne, small_batch):
+    """check_finite in a batched call: a NaN in one member's b makes the call
+    return PNE_EINVAL; with finite inputs the result equals the unchecked
+    call's bit for bit."""
+    probs, _ = small_batch
+    A, b, x, descs = pack(probs)
+    o = pne.make_opts(seed=9, sketch_prec="bf16", qr_prec="fp32", refine_steps=1, check_finite=True)
+    o0 = pne.make_opts(seed=9, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    pne.pne_solve_batched(A, b, x, descs, opts=o0)
+    x0 = host(x).copy()
+    x.zero_()
+    info = host(pne.pne_solve_batched(A, b, x, descs, opts=o))
+    assert np.all(info == 0) and np.array_equal(x0, host(x))
+    d = descs[3]
+    b[d["b_offset"] + 5] = float("nan")
+    with pytest.raises(pne.PneError) as e:
+        pne.pne_solve_batched(A, b, x, descs, opts=o)
+    assert e.value.status == -1

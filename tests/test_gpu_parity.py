@@ -196,6 +196,35 @@ def test_padded_leading_dimension(pne, orc):
         assert relerr(host(x1), host(x2)) <= 1e-12
 
 
+@pytest.mark.parametrize("hpne", [False, True])
+def test_check_finite_rejects_non_finite_inputs(pne, hpne):
+    """pne_opts.check_finite: a NaN in b or an infinity in A (also one in a
+    padded A's m rows, but not NaN in its pad rows) makes the call return
+    PNE_EINVAL before solving; finite inputs give the same x, bit for bit, as
+    the call without the check."""
+    m, n = 1500, 90
+    p = make_problem(m, n, 1e4, 1e-5, seed=1032)
+    A, b = p.numpy_A(), p.numpy_b()
+    fn = pne.hpne_solve if hpne else pne.pne_solve
+    o = pne.make_opts(seed=4, sketch_prec="bf16", qr_prec="fp32", refine_steps=1, check_finite=True)
+    o0 = pne.make_opts(seed=4, sketch_prec="bf16", qr_prec="fp32", refine_steps=1)
+    bd = torch.from_numpy(b).cuda()
+    x0, i0, _ = fn(dev(A), bd, opts=o0)
+    x1, i1, _ = fn(padded(A), bd, opts=o)   # NaN pad rows are not part of A
+    assert int(host(i0)[0]) == 0 and int(host(i1)[0]) == 0
+    assert np.array_equal(host(x0), host(x1))
+    bb = b.copy()
+    bb[m - 1] = np.nan
+    with pytest.raises(pne.PneError) as e:
+        fn(dev(A), torch.from_numpy(bb).cuda(), opts=o)
+    assert e.value.status == -1
+    Ab = A.copy()
+    Ab[17, n - 1] = np.inf
+    with pytest.raises(pne.PneError) as e:
+        fn(padded(Ab), bd, opts=o)
+    assert e.value.status == -1
+
+
 def test_bf16_qr_precision_end_to_end(pne, orc):
     m, n, s = 2000, 80, 240
     p = make_problem(m, n, 1e3, 1e-5, seed=1011)
