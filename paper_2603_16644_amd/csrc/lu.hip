@@ -14,6 +14,8 @@
 //   C22 -= L21 U12 (MFMA GEMM).
 // A zero or non-finite pivot at global column k sets *info = 3000 + k + 1
 // (first only); that column's elimination is skipped.
+#include <utility>
+
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -39,6 +41,13 @@ struct LuShared {
 // with its pivot rows.  LuTail then applies the exchanges to the other
 // columns and forms U12; the trailing update C22 -= L21 U12 follows as an
 // MFMA GEMM launch.
+// f(integral_constant<int, I>) for I = 0, 1, ... in order
+template <typename F, int... I>
+__device__ __forceinline__ void lu_unroll(F& f, std::integer_sequence<int, I...>)
+{
+    (f(std::integral_constant<int, I>{}), ...);
+}
+
 struct LuPanelArgs {
     int64_t n;
     int w;
@@ -71,6 +80,74 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
         const int64_t r = tid + LU_THREADS * q;
 #pragma unroll
         for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
+    }
+    if (w == PW) {
+        // Full panel: the column steps unrolled at compile time, so column k
+        // is x[.][k] itself (no rotation) and the rank-1 update of step k
+        // touches columns k + 1 .. PW - 1 only; otherwise the arithmetic of
+        // the rolled loop below, operation for operation.
+        auto step = [&](auto kc) {
+            constexpr int k = decltype(kc)::value;
+            constexpr int B = k & 1;
+            double best = -1.0;
+            int64_t bidx = INT64_MAX;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t r = tid + LU_THREADS * q;
+                double v = fabs(x[q][k]);
+                if (v != v) v = INFINITY;
+                if (r >= k && r < h && v > best) { best = v; bidx = r; }
+            }
+            wave_argmax(best, bidx);
+            if (lane == 0) { sh.wv[B][wid] = best; sh.wi[B][wid] = bidx; }
+            __syncthreads();
+            double bb = sh.wv[B][0];
+            int64_t p = sh.wi[B][0];
+            for (int i = 1; i < LU_WAVES; ++i)
+                if (sh.wv[B][i] > bb || (sh.wv[B][i] == bb && sh.wi[B][i] < p)) { bb = sh.wv[B][i]; p = sh.wi[B][i]; }
+            if (p < k || p >= h) p = k;
+            if (tid == 0) sh.pivl[k] = (int32_t)p;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t r = tid + LU_THREADS * q;
+                if (r == p)
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) sh.rowP[B][c] = x[q][c];
+                if (r == k)
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) sh.rowK[B][c] = x[q][c];
+            }
+            __syncthreads();
+            const double pv = sh.rowP[B][k];
+            const bool ok = pv != 0.0 && isfinite(pv);
+            if (!ok && tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
+#pragma unroll
+            for (int q = 0; q < RPT; ++q) {
+                const int64_t r = tid + LU_THREADS * q;
+                if (r == k && p != k)
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) x[q][c] = sh.rowP[B][c];
+                if (r == p && p != k)
+#pragma unroll
+                    for (int c = 0; c < PW; ++c) x[q][c] = sh.rowK[B][c];
+                if (ok && r > k && r < h) {
+                    const double l = x[q][k] / pv;
+                    x[q][k] = l;
+#pragma unroll
+                    for (int c = k + 1; c < PW; ++c) x[q][c] -= l * sh.rowP[B][c];
+                }
+            }
+        };
+        lu_unroll(step, std::make_integer_sequence<int, PW>{});
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            const int64_t r = tid + LU_THREADS * q;
+#pragma unroll
+            for (int c = 0; c < PW; ++c)
+                if (r < h) P[r + c * ldc] = x[q][c];
+        }
+        if (tid < w) a.piv[c0 + tid] = (int32_t)(c0 + sh.pivl[tid]);
+        return;
     }
     // Column step k.  The register array is rotated left by one column
     // after every step, so the active column is always x[.][0] and every
