@@ -14,8 +14,6 @@
 //   C22 -= L21 U12 (MFMA GEMM).
 // A zero or non-finite pivot at global column k sets *info = 3000 + k + 1
 // (first only); that column's elimination is skipped.
-#include <utility>
-
 #include "common.h"
 #include "kernels.h"
 #include "launch.h"
@@ -41,13 +39,6 @@ struct LuShared {
 // with its pivot rows.  LuTail then applies the exchanges to the other
 // columns and forms U12; the trailing update C22 -= L21 U12 follows as an
 // MFMA GEMM launch.
-// f(integral_constant<int, I>) for I = 0, 1, ... in order
-template <typename F, int... I>
-__device__ __forceinline__ void lu_unroll(F& f, std::integer_sequence<int, I...>)
-{
-    (f(std::integral_constant<int, I>{}), ...);
-}
-
 struct LuPanelArgs {
     int64_t n;
     int w;
@@ -81,84 +72,18 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
         for (int c = 0; c < PW; ++c) x[q][c] = (r < h && c < w) ? P[r + c * ldc] : 0.0;
     }
-    if (w == PW) {
-        // Full panel: the column steps unrolled at compile time, so column k
-        // is x[.][k] itself (no rotation) and the rank-1 update of step k
-        // touches columns k + 1 .. PW - 1 only; otherwise the arithmetic of
-        // the rolled loop below, operation for operation.
-        auto step = [&](auto kc) {
-            constexpr int k = decltype(kc)::value;
-            constexpr int B = k & 1;
-            double best = -1.0;
-            int64_t bidx = INT64_MAX;
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int64_t r = tid + LU_THREADS * q;
-                double v = fabs(x[q][k]);
-                if (v != v) v = INFINITY;
-                if (r >= k && r < h && v > best) { best = v; bidx = r; }
-            }
-            wave_argmax(best, bidx);
-            if (lane == 0) { sh.wv[B][wid] = best; sh.wi[B][wid] = bidx; }
-            __syncthreads();
-            double bb = sh.wv[B][0];
-            int64_t p = sh.wi[B][0];
-            for (int i = 1; i < LU_WAVES; ++i)
-                if (sh.wv[B][i] > bb || (sh.wv[B][i] == bb && sh.wi[B][i] < p)) { bb = sh.wv[B][i]; p = sh.wi[B][i]; }
-            if (p < k || p >= h) p = k;
-            if (tid == 0) sh.pivl[k] = (int32_t)p;
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int64_t r = tid + LU_THREADS * q;
-                if (r == p)
-#pragma unroll
-                    for (int c = 0; c < PW; ++c) sh.rowP[B][c] = x[q][c];
-                if (r == k)
-#pragma unroll
-                    for (int c = 0; c < PW; ++c) sh.rowK[B][c] = x[q][c];
-            }
-            __syncthreads();
-            const double pv = sh.rowP[B][k];
-            const bool ok = pv != 0.0 && isfinite(pv);
-            if (!ok && tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
-#pragma unroll
-            for (int q = 0; q < RPT; ++q) {
-                const int64_t r = tid + LU_THREADS * q;
-                if (r == k && p != k)
-#pragma unroll
-                    for (int c = 0; c < PW; ++c) x[q][c] = sh.rowP[B][c];
-                if (r == p && p != k)
-#pragma unroll
-                    for (int c = 0; c < PW; ++c) x[q][c] = sh.rowK[B][c];
-                if (ok && r > k && r < h) {
-                    const double l = x[q][k] / pv;
-                    x[q][k] = l;
-#pragma unroll
-                    for (int c = k + 1; c < PW; ++c) x[q][c] -= l * sh.rowP[B][c];
-                }
-            }
-        };
-        lu_unroll(step, std::make_integer_sequence<int, PW>{});
-#pragma unroll
-        for (int q = 0; q < RPT; ++q) {
-            const int64_t r = tid + LU_THREADS * q;
-#pragma unroll
-            for (int c = 0; c < PW; ++c)
-                if (r < h) P[r + c * ldc] = x[q][c];
-        }
-        if (tid < w) a.piv[c0 + tid] = (int32_t)(c0 + sh.pivl[tid]);
-        return;
-    }
-    // Column step k.  The register array is rotated left by one column
-    // after every step, so the active column is always x[.][0] and every
-    // register index is a compile-time constant; after step k the columns
-    // already factored sit at the end (positions PW - k .. PW - 1).  Two
+    // Column step k with the active column at register position J (a
+    // compile-time constant).  The register row is rotated left after every
+    // block of steps, so that every register index stays a compile-time
+    // constant; after step k the columns already factored sit at the end
+    // (positions PW - k .. PW - 1) or, inside a block, before J.  Two
     // barriers per step: after the wavefront argmax candidates are published
     // (every thread then forms the pivot row itself) and after the owners of
     // rows k and p publish them.  The owner of the pivot row also publishes
     // it with the factored columns zeroed (rowPu), which the rank-1 update
     // uses, so that no thread tests column positions.
-    for (int k = 0; k < w; ++k) {
+    auto colstep = [&](auto jc, int k) {
+        constexpr int J = decltype(jc)::value;
         const int B = k & 1;
         // argmax |x(r, k)| over r >= k, first index on ties; a NaN counts as
         // +inf, so a column holding one selects a non-finite pivot
@@ -167,7 +92,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
-            double v = fabs(x[q][0]);
+            double v = fabs(x[q][J]);
             if (v != v) v = INFINITY;
             if (r >= k && r < h && v > best) { best = v; bidx = r; }
         }
@@ -180,7 +105,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
             if (sh.wv[B][i] > bb || (sh.wv[B][i] == bb && sh.wi[B][i] < p)) { bb = sh.wv[B][i]; p = sh.wi[B][i]; }
         if (p < k || p >= h) p = k;   // no candidate: keep the row in place
         if (tid == 0) sh.pivl[k] = (int32_t)p;
-        const int live = PW - k;      // positions 0 .. live - 1 are not factored yet
+        const int live = PW - k + J;  // positions J .. live - 1 are not factored yet
 #pragma unroll
         for (int q = 0; q < RPT; ++q) {
             const int64_t r = tid + LU_THREADS * q;
@@ -195,7 +120,7 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
                 for (int c = 0; c < PW; ++c) sh.rowK[B][c] = x[q][c];
         }
         __syncthreads();
-        const double pv = sh.rowP[B][0];
+        const double pv = sh.rowP[B][J];
         const bool ok = pv != 0.0 && isfinite(pv);
         if (!ok && tid == 0 && *info == 0) *info = 3000 + (int32_t)(c0 + k) + 1;
 #pragma unroll
@@ -210,17 +135,41 @@ __device__ void LuPanel<RPT, PW>::run(const LuPanelArgs& a, int, int)
                 for (int c = 0; c < PW; ++c) x[q][c] = sh.rowK[B][c];
             // multiplier and rank-1 update of the rows below k
             if (ok && r > k && r < h) {
-                const double l = x[q][0] / pv;
-                x[q][0] = l;
+                const double l = x[q][J] / pv;
+                x[q][J] = l;
 #pragma unroll
-                for (int c = 1; c < PW; ++c) x[q][c] -= l * sh.rowPu[B][c];
+                for (int c = J + 1; c < PW; ++c) x[q][c] -= l * sh.rowPu[B][c];
             }
-            // rotate: the factored column moves to the end
-            const double x0 = x[q][0];
-#pragma unroll
-            for (int c = 0; c < PW - 1; ++c) x[q][c] = x[q][c + 1];
-            x[q][PW - 1] = x0;
         }
+    };
+    // rotate the register row left by S positions
+    auto rotate = [&](auto sc) {
+        constexpr int S = decltype(sc)::value;
+#pragma unroll
+        for (int q = 0; q < RPT; ++q) {
+            double t[S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) t[c] = x[q][c];
+#pragma unroll
+            for (int c = 0; c < PW - S; ++c) x[q][c] = x[q][c + S];
+#pragma unroll
+            for (int c = 0; c < S; ++c) x[q][PW - S + c] = t[c];
+        }
+    };
+    // blocks of four steps (one rotation per block), then single steps
+    int k = 0;
+#pragma unroll 1
+    for (; k + 4 <= w; k += 4) {
+        colstep(std::integral_constant<int, 0>{}, k);
+        colstep(std::integral_constant<int, 1>{}, k + 1);
+        colstep(std::integral_constant<int, 2>{}, k + 2);
+        colstep(std::integral_constant<int, 3>{}, k + 3);
+        rotate(std::integral_constant<int, 4>{});
+    }
+#pragma unroll 1
+    for (; k < w; ++k) {
+        colstep(std::integral_constant<int, 0>{}, k);
+        rotate(std::integral_constant<int, 1>{});
     }
     // position c now holds panel column (c + w) mod PW
 #pragma unroll
