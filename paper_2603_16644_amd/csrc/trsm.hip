@@ -64,19 +64,18 @@ __device__ void TrsmLeaf<T, TRANS_LOWER, UNIT, NT>::run(const TrsmLeafArgs& a, i
     T x[LEAF];
 #pragma unroll
     for (int c = 0; c < LEAF; ++c) x[c] = (c < w) ? Xi[i * rs + c * csi] : (T)0;
-    // column-oriented substitution: once y_c is final it is removed from every
-    // later entry; y_j still accumulates its terms in the order k = 0, 1, ...
+    // column-oriented substitution: once y_c is final it is stored and
+    // removed from every later entry (the stores then overlap the rest of
+    // the work); y_j still accumulates its terms in the order k = 0, 1, ...
 #pragma unroll
     for (int c = 0; c < LEAF; ++c) {
         if (c < w) {
             if (!UNIT) x[c] = x[c] * rd[c];
+            X[i * rs + c * cs] = x[c];   // final: stored while the later columns are formed
 #pragma unroll
             for (int j = c + 1; j < LEAF; ++j) x[j] -= x[c] * Rs[c * LEAF + j];
         }
     }
-#pragma unroll
-    for (int c = 0; c < LEAF; ++c)
-        if (c < w) X[i * rs + c * cs] = x[c];
 }
 
 template <typename T, bool TL, bool UNIT>
