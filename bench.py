@@ -352,7 +352,7 @@ def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not built)"}))
+                                   "(how the solve would shard over GPUs is a design note only; no multi-GPU path is built)"}))
         sys.exit(2)
     import torch
 
