@@ -104,3 +104,30 @@ def test_batched_workspace_sizing_runs_on_host(pne):
     assert L.pne_batched_workspace_size(3, p, ctypes.byref(o), 0) == 0
     one = ctypes.c_void_p(256)
     assert L.pne_solve_batched(3, p, one, one, one, ctypes.byref(o), 0, one, 1 << 30, one, None) == -1
+
+
+def test_no_cpu_fallback():
+    """Without the built library the binding raises, and CPU tensors are
+    refused: nothing computes the solve outside the HIP library."""
+    import subprocess
+    import sys
+    code = (
+        "import paper_2603_16644_amd._lib as l\n"
+        "l.LIB_PATH = '/nonexistent/libpne.so'\n"
+        "import paper_2603_16644_amd as p, torch\n"
+        "try:\n"
+        "    p.lib()\n"
+        "    raise SystemExit('library call did not raise')\n"
+        "except RuntimeError:\n"
+        "    pass\n"
+        "A = torch.randn(50, 5, dtype=torch.float64)\n"
+        "b = torch.randn(50, dtype=torch.float64)\n"
+        "for fn in (p.pne_solve, p.hpne_solve):\n"
+        "    try:\n"
+        "        fn(A, b)\n"
+        "        raise SystemExit('CPU tensors were accepted')\n"
+        "    except ValueError:\n"
+        "        pass\n"
+        "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
